@@ -229,8 +229,9 @@ static inline uint64_t draw(uint64_t seed, uint64_t inst, uint64_t b, uint64_t s
  *   - temperatures temps[s], one per sweep (the caller passes the schedule);
  *   - a sweep visits variables 0, 1, ..., n-1 in order;
  *   - visiting i: dE = (1 - 2 x_i) g_i(x), exact; accept iff dE <= 0 or
- *     u < exp(-dE / T) with u from draw(seed, inst, b, s, i, 0), both in
- *     double precision; on acceptance flip x_i and add dE to E;
+ *     u < exp(-dE * beta) with beta = 1 / T and u from draw(seed, inst, b,
+ *     s, i, 0), all in double precision; on acceptance flip x_i and add dE
+ *     to E;
  *   - initial state: given, or bit i = top bit of draw(seed, inst, b, 0, i, 1);
  *   - best state: the initial one, then after every sweep the current state
  *     if its energy is strictly lower.
@@ -272,7 +273,7 @@ int orc_anneal(int n_vars, int n_mono, const int64_t* mono_ptr, const int32_t* m
     i128 best = e;
     memcpy(bx, x, (size_t)n_vars);
     for (int s = 0; s < S; ++s) {
-      double T = temps[s];
+      double beta = 1.0 / temps[s]; /* inverse temperature of this sweep */
       for (int i = 0; i < n_vars; ++i) {
         if (attempt && !attempt[((size_t)(b / 16) * (size_t)S + (size_t)s) * (size_t)n_vars + (size_t)i]) continue;
         i128 g = 0;
@@ -286,7 +287,7 @@ int orc_anneal(int n_vars, int n_mono, const int64_t* mono_ptr, const int32_t* m
         i128 de = x[i] ? -g : g;
         double ded = fixed_to_double(de, s_scale);
         double u = u01(draw(seed, inst, (uint64_t)b, (uint64_t)s, i, 0));
-        if (ded <= 0.0 || u < exp(-ded / T)) {
+        if (ded <= 0.0 || u < exp(-ded * beta)) {
           x[i] ^= 1;
           e += de;
           total_acc++;
