@@ -1,0 +1,220 @@
+/*
+ * hobo.h -- C-ABI of the MI355X (gfx950) HOBO engine.
+ *
+ * The engine evaluates higher-order binary optimisation (HOBO) objectives
+ *     f(x) = offset + sum_S w_S prod_{i in S} x_i,   x in {0,1}^N,
+ * (HOBOTAN, arXiv 2407.19987, Sec. II.B: the QUBO form with terms a_i x_i and
+ * b_ij x_i x_j, extended by c_ijk x_i x_j x_k and higher orders) for large
+ * batches of candidate bit vectors, and searches them with batched
+ * single-flip Metropolis annealing (Sec. II.D.1).  The paper stores the
+ * coefficients as an order-k tensor whose lower-order terms repeat their
+ * smallest index (Sec. III.C, IV.A) and contracts it with a matrix of many
+ * candidate vectors at once (Sec. IV.C, the "tensor batch system");
+ * hobo_energy computes exactly that contraction, row by row.
+ *
+ * Conventions
+ * -----------
+ * - Every function returns a hobo_status (0 = HOBO_OK).  No exception or
+ *   signal crosses the ABI.  hobo_last_error() returns a thread-local
+ *   description of the last failure on the calling thread.
+ * - All argument checks happen before any HIP call, so invalid arguments
+ *   never reach the GPU.
+ * - Bit vectors are uint64 words in [W][B] order, W = ceil(N/64): variable i
+ *   of row b is bit (i & 63) of word x_bits[(i >> 6) * B + b].  Bits at or
+ *   above N in the last word must be zero.
+ * - Device buffers (x_bits, outputs) are allocated by the caller and must be
+ *   device memory of the current HIP device.  All device work is enqueued on
+ *   the caller's stream (a hipStream_t passed as void*, NULL = default
+ *   stream); results are valid once the caller synchronises that stream.
+ * - A hobo_tensor is owned by the library until hobo_free_tensor.  It is
+ *   immutable once built, except that device layouts are created on first use
+ *   of a (function, precision) pair; that first use blocks the host and must
+ *   not happen during stream capture -- call hobo_tensor_prepare first.
+ * - Energies exclude the constant offset (the paper prints the energy
+ *   without it); the offset is returned by hobo_build_tensor.
+ * - Limits: 1 <= N <= 256 variables, order <= 7, B >= 1.
+ */
+#ifndef HOBO_H
+#define HOBO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hobo_status;
+enum {
+  HOBO_OK = 0,
+  HOBO_ERR_INVALID_ARG = 1, /* null pointer, bad size, index out of range */
+  HOBO_ERR_ORDER = 2,       /* order above max_order or above the engine limit */
+  HOBO_ERR_RANGE = 3,       /* integer instance not exactly representable */
+  HOBO_ERR_PRECISION = 4,   /* precision not valid for this tensor / function */
+  HOBO_ERR_NO_DEVICE = 5,   /* no HIP device */
+  HOBO_ERR_OOM = 6,         /* device allocation failed */
+  HOBO_ERR_HIP = 7,         /* a HIP runtime call failed */
+  HOBO_ERR_UNSUPPORTED = 8  /* valid request the engine does not implement */
+};
+
+/* coefficient types */
+enum { HOBO_COEFF_INT64 = 0, HOBO_COEFF_F64 = 1 };
+
+/* arithmetic of the contraction kernels
+ *  FP32   : FP32 coefficients, FP32 matrix-core products and sums
+ *  BF16X2 : coefficient c (rounded to FP32) split as hi = bf16(c),
+ *           lo = bf16(c - hi); two BF16 matrix-core passes, FP32 sums
+ *  BF16X3 : three-way split hi + mid + lo (exact for normal FP32 values)
+ *  INT8X4 : integer coefficients as four balanced base-256 digits in
+ *           [-128, 127]; INT8 matrix-core products, int32 per-digit sums,
+ *           recombined exactly in int64.  Integer tensors only.
+ *  FP64   : double-precision term-by-term sums (hobo_energy only; used to
+ *           rescore states) */
+enum {
+  HOBO_PREC_FP32 = 0,
+  HOBO_PREC_BF16X2 = 1,
+  HOBO_PREC_BF16X3 = 2,
+  HOBO_PREC_INT8X4 = 3,
+  HOBO_PREC_FP64 = 4
+};
+
+typedef struct hobo_tensor hobo_tensor;
+
+typedef struct {
+  int32_t n_vars;
+  int32_t order;
+  int32_t is_integer;
+  int32_t reserved;
+  int64_t n_monomials;
+  int64_t n_per_order[8]; /* monomials of each order 0..7 (order 0 always 0) */
+  int64_t offset_i64;     /* offset of an integer tensor */
+  double offset_f64;      /* offset as double (both kinds) */
+  int64_t device_bytes;   /* device memory held by the tensor's layouts */
+} hobo_tensor_info;
+
+/* Build a tensor from a raw term list (HOBOTAN Sec. III.C / IV.A compile step).
+ *  n_vars     : N, 1..256; variables are 0..N-1 (drop unused variables first,
+ *               Sec. IV.D)
+ *  max_order  : 0 = infer; otherwise HOBO_ERR_ORDER if the instance is larger
+ *  n_terms    : number of terms (>= 0)
+ *  term_ptr   : host int64[n_terms+1], CSR offsets into term_idx, term_ptr[0] = 0
+ *  term_idx   : host int32 variable indices; repeats inside a term collapse
+ *               (x*x = x); an empty term is a constant and goes to the offset
+ *  coeff      : host int64[n_terms] (HOBO_COEFF_INT64) or double[n_terms]
+ *               (HOBO_COEFF_F64); duplicate monomials are summed, zero sums
+ *               dropped
+ *  out        : receives the new handle (unchanged on error)
+ *  offset_out : host int64* (integer) or double* (real), may be NULL
+ * Integer sums that overflow int64 give HOBO_ERR_RANGE. */
+hobo_status hobo_build_tensor(int32_t n_vars, int32_t max_order, int64_t n_terms,
+                              const int64_t* term_ptr, const int32_t* term_idx, const void* coeff,
+                              int32_t coeff_type, hobo_tensor** out, void* offset_out);
+
+/* Release a tensor and all its device memory (NULL is accepted). */
+hobo_status hobo_free_tensor(hobo_tensor* t);
+
+/* Host-side description of a tensor. */
+hobo_status hobo_tensor_info_get(const hobo_tensor* t, hobo_tensor_info* info);
+
+/* Copy the canonical monomials to the host: mono_ptr int64[n_monomials+1],
+ * mono_idx int32[mono_ptr[n]], weights int64 (integer) or double (real).
+ * Each array may be NULL to skip it; capacities are checked. */
+hobo_status hobo_tensor_monomials(const hobo_tensor* t, int64_t* mono_ptr, int64_t ptr_cap,
+                                  int32_t* mono_idx, int64_t idx_cap, void* weights,
+                                  int64_t w_cap);
+
+/* Dense N^k tensor in the paper's layout (Sec. III.C): a monomial of size
+ * r < k is stored at the index tuple that repeats its smallest variable
+ * k - r + 1 times followed by its other variables in increasing order; all
+ * other entries are 0.  host_out: int64 or double [N^k], row-major, with
+ * N^k <= capacity and N^k <= 2^26. */
+hobo_status hobo_tensor_export_dense(const hobo_tensor* t, void* host_out, int64_t capacity);
+
+/* Create the device layouts of `t` for the functions in `fn_mask`
+ * (1 = hobo_energy, 2 = hobo_local_fields, 4 = hobo_anneal_batch) and the
+ * precisions in `prec_mask` (bit p = precision p).  Blocks the host. */
+hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_mask);
+
+/* Batched energies E_b = sum_S w_S prod_{i in S} x_{b,i} (offset excluded),
+ * the paper's batch contraction (Sec. IV.C) of its HOBO tensor (Sec. II.C).
+ *  x_bits    : device uint64 [W][B]
+ *  B         : rows, >= 1
+ *  precision : FP32 | BF16X2 | BF16X3 | INT8X4 (integer tensors) | FP64
+ *  e_out     : device int64[B] for integer tensors, double[B] for real ones
+ *  stream    : hipStream_t */
+hobo_status hobo_energy(const hobo_tensor* t, const uint64_t* x_bits, int64_t B,
+                        int32_t precision, void* e_out, void* stream);
+
+/* Batched single-flip energy changes dE_{b,i} = f(x_b xor e_i) - f(x_b)
+ * = (1 - 2 x_{b,i}) g_{b,i}, with the local field
+ * g_{b,i} = sum_{S containing i} w_S prod_{j in S, j != i} x_{b,j},
+ * the quantity the Metropolis search (Sec. II.D.1) needs for every bit.
+ *  precision : FP32 | BF16X2 | BF16X3 | INT8X4 (integer tensors)
+ *  de_out    : device [B][N] row-major: int64 for integer tensors, float
+ *              otherwise
+ *  e_out     : optional device energies (as in hobo_energy), computed from
+ *              the per-order fields with Euler's identity
+ *              sum_i x_i g_i^(r) = r E^(r). */
+hobo_status hobo_local_fields(const hobo_tensor* t, const uint64_t* x_bits, int64_t B,
+                              int32_t precision, void* de_out, void* e_out, void* stream);
+
+/* ------------------------------------------------------------- annealing */
+enum { HOBO_INIT_RANDOM = 0, HOBO_INIT_GIVEN = 1 };
+enum { HOBO_PROPOSAL_METROPOLIS = 0, HOBO_PROPOSAL_MASKED = 1 };
+enum { HOBO_LAUNCH_PER_INSTANCE = 0, HOBO_LAUNCH_PERSISTENT = 1, HOBO_LAUNCH_GRAPH = 2 };
+
+typedef struct {
+  int32_t sweeps;      /* S >= 0 */
+  int32_t precision;   /* FP32 | BF16X2 | BF16X3 | INT8X4 */
+  double t_start;      /* T_0 > 0 */
+  double t_end;        /* T_{S-1} > 0; T_s = T_0 (T_end/T_0)^(s/(S-1)) */
+  uint64_t seed;
+  int32_t init;        /* HOBO_INIT_RANDOM or HOBO_INIT_GIVEN */
+  int32_t proposal;    /* HOBO_PROPOSAL_METROPOLIS, or MASKED with attempt masks */
+  const uint8_t* attempt; /* MASKED: device uint8 [ceil(B/16)][S][N] per instance,
+                             concatenated; 1 = the 16-replica group visits the bit */
+  int32_t waves_per_block; /* 0 = tuned default */
+  int32_t reserved;
+} hobo_anneal_params;
+
+/* Batched single-flip Metropolis simulated annealing (Sec. II.D.1) over one
+ * or several instances.  Replica b of instance j:
+ *   - initial state: x_inout (GIVEN) or bit i = top bit of Philox4x64-10 word
+ *     i%4 at counter (b, 0, i/4, 1), key (seed, j) (RANDOM);
+ *   - sweep s visits variables 0..N-1 in order (skipping bits whose attempt
+ *     mask is 0 in MASKED mode); at variable i it draws
+ *     u = (r >> 11) 2^-53 from word i%4 of Philox4x64-10 at counter
+ *     (b, s, i/4, 0), key (seed, j), computes dE_i in the tensor precision,
+ *     and accepts iff dE_i <= 0 or u < exp(-dE_i * beta_s) in double, with
+ *     beta_s = 1 / T_s; on acceptance x_i flips and E += dE_i (double);
+ *   - the best state is the initial one, then after each sweep the current
+ *     one if its tracked energy is strictly lower.
+ *  tensors     : host array of n_instances handles
+ *  replicas    : host int64[n_instances], B_j >= 1
+ *  x_inout     : device uint64, instance j's [W_j][B_j] block after those of
+ *                instances < j; in: initial states (GIVEN), out: final states
+ *  best_x_out  : device uint64, same layout: best states
+ *  best_e_out  : device, one value per replica (instances concatenated):
+ *                exact int64 energies of the best states when every instance
+ *                is integer, else double energies recomputed in FP64
+ *  trace_out   : optional device double [n_instances][S]: minimum over the
+ *                instance's replicas of the tracked best energy after each sweep
+ *  launch_mode : PER_INSTANCE (one launch sequence per instance),
+ *                PERSISTENT (one persistent launch over all instances), or
+ *                GRAPH (the persistent sequence captured once in a hipGraph
+ *                and launched from it) -- identical results */
+hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances,
+                              const int64_t* replicas, const hobo_anneal_params* params,
+                              uint64_t* x_inout, uint64_t* best_x_out, void* best_e_out,
+                              double* trace_out, int32_t launch_mode, void* stream);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* hobo_last_error(void);
+
+/* Library version string. */
+const char* hobo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOBO_H */

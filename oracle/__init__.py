@@ -214,18 +214,64 @@ def fields(canon: Canonical, bits: np.ndarray):
     return g, de
 
 
+def _rows(canon: Canonical, bits: np.ndarray) -> np.ndarray:
+    bits = np.asarray(bits, dtype=np.uint64)
+    n = canon.n_vars
+    x = np.zeros((bits.shape[1], n), dtype=bool)
+    for i in range(n):
+        x[:, i] = ((bits[i >> 6] >> np.uint64(i & 63)) & np.uint64(1)).astype(bool)
+    return x
+
+
 def active_scale(canon: Canonical, bits: np.ndarray) -> np.ndarray:
     """s(x) = sqrt(sum over active monomials of w_S^2): the size of the terms
-    that make up E(x), used as the floor of the relative error criterion."""
-    sq = Canonical(canon.n_vars, canon.order, canon.monos, [float(w) ** 2 for w in canon.weights], 0, False)
-    return np.sqrt(np.maximum(energy(sq, bits), 0.0))
+    that make up E(x), used as the floor of the relative error criterion
+    (a tolerance scale, summed in plain double precision)."""
+    x = _rows(canon, bits)
+    out = np.zeros(x.shape[0])
+    by_len: dict = {}
+    for m, w in zip(canon.monos, canon.weights):
+        by_len.setdefault(len(m), ([], []))
+        by_len[len(m)][0].append(m)
+        by_len[len(m)][1].append(float(w) ** 2)
+    for r, (ms, w2) in by_len.items():
+        idx = np.array(ms, dtype=np.int64)
+        w2 = np.array(w2)
+        for b0 in range(0, x.shape[0], 256):
+            xb = x[b0:b0 + 256]
+            act = np.ones((xb.shape[0], len(ms)), dtype=bool)
+            for q in range(r):
+                act &= xb[:, idx[:, q]]
+            out[b0:b0 + 256] += act.astype(np.float64) @ w2
+    return np.sqrt(out)
 
 
 def field_scale(canon: Canonical, bits: np.ndarray) -> np.ndarray:
-    """[B][N] sqrt(sum over monomials S containing i with S\\{i} active of w_S^2)."""
-    sq = Canonical(canon.n_vars, canon.order, canon.monos, [float(w) ** 2 for w in canon.weights], 0, False)
-    g, _ = fields(sq, bits)
-    return np.sqrt(np.maximum(g, 0.0))
+    """[B][N] sqrt(sum over monomials S containing i with S minus i active of
+    w_S^2): the tolerance scale of the field g_i (plain double precision)."""
+    x = _rows(canon, bits)
+    n = canon.n_vars
+    out = np.zeros((x.shape[0], n))
+    by_len: dict = {}
+    for m, w in zip(canon.monos, canon.weights):
+        by_len.setdefault(len(m), ([], []))
+        by_len[len(m)][0].append(m)
+        by_len[len(m)][1].append(float(w) ** 2)
+    for r, (ms, w2) in by_len.items():
+        idx = np.array(ms, dtype=np.int64)
+        w2 = np.array(w2)
+        for p in range(r):
+            onehot = np.zeros((len(ms), n))
+            onehot[np.arange(len(ms)), idx[:, p]] = 1.0
+            weighted = onehot * w2[:, None]
+            for b0 in range(0, x.shape[0], 256):
+                xb = x[b0:b0 + 256]
+                act = np.ones((xb.shape[0], len(ms)), dtype=bool)
+                for q in range(r):
+                    if q != p:
+                        act &= xb[:, idx[:, q]]
+                out[b0:b0 + 256] += act.astype(np.float64) @ weighted
+    return np.sqrt(out)
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,605 @@
+// C-ABI entry points of the HOBO engine (declared in include/hobo.h).
+// Every argument is checked on the host before any HIP call; failures return
+// a status code and leave a thread-local message for hobo_last_error().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hobo_internal.h"
+#include "../../include/hobo.h"
+
+struct hobo_tensor {
+  hobo::Tensor t;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+hobo_status fail(hobo_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+hobo_status ok() { return HOBO_OK; }
+
+hobo_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return HOBO_OK;
+  (void)hipGetLastError();
+  return fail(e == hipErrorOutOfMemory ? HOBO_ERR_OOM : HOBO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hobo_status need_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(HOBO_ERR_NO_DEVICE, "no HIP device available");
+  }
+  return HOBO_OK;
+}
+
+bool valid_prec(int p) { return p >= HOBO_PREC_FP32 && p <= HOBO_PREC_FP64; }
+
+// Tile shape of the evaluation kernels: 16*rt replicas x 16*ct columns per
+// wave.  Narrower column groups give more waves when B is small.
+void eval_shape(const hobo::Tensor& t, int prec, int64_t B, int* rt, int* ct) {
+  int T = (t.n_vars + 15) / 16;
+  int c = 1;
+  while (c < T && c < 8) c *= 2;
+  if (prec == HOBO_PREC_INT8X4 && c > 4) c = 4;
+  auto waves = [&](int cc, int rr) { return ((B + 16 * rr - 1) / (16 * rr)) * ((T + cc - 1) / cc); };
+  while (c > 1 && waves(c, 1) < 1024) c /= 2;
+  int r = waves(c, 2) >= 2048 ? 2 : 1;
+  const char* env_rt = std::getenv("HOBO_EVAL_RT");
+  const char* env_ct = std::getenv("HOBO_EVAL_CT");
+  if (env_rt) r = std::max(1, std::min(2, std::atoi(env_rt)));
+  if (env_ct) {
+    int v = std::atoi(env_ct);
+    c = v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 1;
+    if (prec == HOBO_PREC_INT8X4 && c > 4) c = 4;
+  }
+  *rt = r;
+  *ct = c;
+}
+
+hobo_status check_bits_args(const hobo_tensor* t, const void* x_bits, int64_t B, int32_t precision) {
+  if (!t) return fail(HOBO_ERR_INVALID_ARG, "tensor is NULL");
+  if (!x_bits) return fail(HOBO_ERR_INVALID_ARG, "x_bits is NULL");
+  if (B < 1) return fail(HOBO_ERR_INVALID_ARG, "B must be >= 1");
+  if (B > (int64_t)1 << 40) return fail(HOBO_ERR_INVALID_ARG, "B too large");
+  if (!valid_prec(precision)) return fail(HOBO_ERR_INVALID_ARG, "unknown precision");
+  if (precision == HOBO_PREC_INT8X4 && !t->t.integer)
+    return fail(HOBO_ERR_PRECISION, "INT8X4 precision needs an integer tensor");
+  return HOBO_OK;
+}
+
+// ------------------------------------------------------------ graph cache
+// Annealing setups (device tables, workspace, captured graph) are cached by
+// their full argument list, so repeated identical calls only enqueue kernels
+// (or launch the graph).  Entries that name a tensor die with it.
+struct AnnealEntry {
+  std::vector<uint64_t> key;
+  int32_t mode = 0;
+  void* work = nullptr;
+  hobo::AnnealTables tb;
+  std::vector<int> item_first;
+  std::vector<int> ct_of, nw_of;
+  int ct = 1, nw = 1;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_anneal_mu;
+std::list<AnnealEntry> g_anneal;  // most recent first
+
+void release_entry(AnnealEntry& e) {
+  (void)hipDeviceSynchronize();
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.work) (void)hipFree(e.work);
+  e.exec = nullptr;
+  e.work = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hobo_last_error(void) { return g_err.c_str(); }
+const char* hobo_version(void) { return "hobo-mi355x 0.1 (gfx950)"; }
+
+hobo_status hobo_build_tensor(int32_t n_vars, int32_t max_order, int64_t n_terms, const int64_t* term_ptr,
+                              const int32_t* term_idx, const void* coeff, int32_t coeff_type, hobo_tensor** out,
+                              void* offset_out) {
+  g_err.clear();
+  if (!out) return fail(HOBO_ERR_INVALID_ARG, "out is NULL");
+  if (n_vars < 1 || n_vars > hobo::kMaxVars)
+    return fail(HOBO_ERR_INVALID_ARG, "n_vars must be in [1, 256]");
+  if (max_order < 0) return fail(HOBO_ERR_INVALID_ARG, "max_order must be >= 0");
+  if (n_terms < 0) return fail(HOBO_ERR_INVALID_ARG, "n_terms must be >= 0");
+  if (coeff_type != HOBO_COEFF_INT64 && coeff_type != HOBO_COEFF_F64)
+    return fail(HOBO_ERR_INVALID_ARG, "unknown coeff_type");
+  if (!term_ptr) return fail(HOBO_ERR_INVALID_ARG, "term_ptr is NULL");
+  if (n_terms > 0 && !coeff) return fail(HOBO_ERR_INVALID_ARG, "coeff is NULL");
+  if (term_ptr[0] != 0) return fail(HOBO_ERR_INVALID_ARG, "term_ptr[0] must be 0");
+  for (int64_t i = 0; i < n_terms; ++i)
+    if (term_ptr[i + 1] < term_ptr[i]) return fail(HOBO_ERR_INVALID_ARG, "term_ptr must be non-decreasing");
+  const int64_t nnz = term_ptr[n_terms];
+  if (nnz > 0 && !term_idx) return fail(HOBO_ERR_INVALID_ARG, "term_idx is NULL");
+  for (int64_t p = 0; p < nnz; ++p)
+    if (term_idx[p] < 0 || term_idx[p] >= n_vars)
+      return fail(HOBO_ERR_INVALID_ARG, "variable index " + std::to_string(term_idx[p]) + " outside [0, n_vars)");
+  if (coeff_type == HOBO_COEFF_F64) {
+    const double* c = static_cast<const double*>(coeff);
+    for (int64_t i = 0; i < n_terms; ++i)
+      if (!std::isfinite(c[i])) return fail(HOBO_ERR_INVALID_ARG, "non-finite coefficient");
+  }
+  hobo_tensor* h = new (std::nothrow) hobo_tensor();
+  if (!h) return fail(HOBO_ERR_OOM, "host allocation failed");
+  std::string err;
+  int st = hobo::canonicalize(n_vars, max_order, n_terms, term_ptr, term_idx, coeff, coeff_type, &h->t, &err);
+  if (st != HOBO_OK) {
+    delete h;
+    return fail(st, err);
+  }
+  int dev = -1;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  }
+  (void)hipGetLastError();
+  h->t.device = dev;
+  if (offset_out) {
+    if (h->t.integer)
+      *static_cast<int64_t*>(offset_out) = h->t.offset_i;
+    else
+      *static_cast<double*>(offset_out) = h->t.offset_f;
+  }
+  *out = h;
+  return ok();
+}
+
+hobo_status hobo_free_tensor(hobo_tensor* t) {
+  g_err.clear();
+  if (!t) return ok();
+  {
+    std::lock_guard<std::mutex> lock(g_anneal_mu);
+    for (auto it = g_anneal.begin(); it != g_anneal.end();) {
+      bool uses = false;
+      for (auto v : it->key) uses = uses || v == (uint64_t)(uintptr_t)t;
+      if (uses) {
+        release_entry(*it);
+        it = g_anneal.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  delete t;
+  return ok();
+}
+
+hobo_status hobo_tensor_info_get(const hobo_tensor* t, hobo_tensor_info* info) {
+  g_err.clear();
+  if (!t || !info) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_vars = t->t.n_vars;
+  info->order = t->t.order;
+  info->is_integer = t->t.integer ? 1 : 0;
+  info->n_monomials = t->t.n_mono();
+  for (size_t r = 0; r < t->t.n_per_order.size() && r < 8; ++r) info->n_per_order[r] = t->t.n_per_order[r];
+  info->offset_i64 = t->t.offset_i;
+  info->offset_f64 = t->t.offset_f;
+  int64_t bytes = 0;
+  hobo_tensor* tm = const_cast<hobo_tensor*>(t);
+  {
+    std::lock_guard<std::mutex> lock(tm->t.mu);
+    for (auto& kv : tm->t.packed) bytes += (int64_t)kv.second->bytes;
+    if (tm->t.terms) bytes += (int64_t)tm->t.terms->bytes;
+  }
+  info->device_bytes = bytes;
+  return ok();
+}
+
+hobo_status hobo_tensor_monomials(const hobo_tensor* t, int64_t* mono_ptr, int64_t ptr_cap, int32_t* mono_idx,
+                                  int64_t idx_cap, void* weights, int64_t w_cap) {
+  g_err.clear();
+  if (!t) return fail(HOBO_ERR_INVALID_ARG, "tensor is NULL");
+  const hobo::Tensor& T = t->t;
+  const int64_t nm = T.n_mono();
+  if (mono_ptr) {
+    if (ptr_cap < nm + 1) return fail(HOBO_ERR_INVALID_ARG, "mono_ptr capacity too small");
+    for (int64_t m = 0; m <= nm; ++m) mono_ptr[m] = T.mono_ptr[(size_t)m];
+  }
+  if (mono_idx) {
+    if (idx_cap < (int64_t)T.mono_idx.size()) return fail(HOBO_ERR_INVALID_ARG, "mono_idx capacity too small");
+    for (size_t p = 0; p < T.mono_idx.size(); ++p) mono_idx[p] = T.mono_idx[p];
+  }
+  if (weights) {
+    if (w_cap < nm) return fail(HOBO_ERR_INVALID_ARG, "weights capacity too small");
+    for (int64_t m = 0; m < nm; ++m) {
+      if (T.integer)
+        static_cast<int64_t*>(weights)[m] = T.w_i[(size_t)m];
+      else
+        static_cast<double*>(weights)[m] = T.w_f[(size_t)m];
+    }
+  }
+  return ok();
+}
+
+hobo_status hobo_tensor_export_dense(const hobo_tensor* t, void* host_out, int64_t capacity) {
+  g_err.clear();
+  if (!t || !host_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  const hobo::Tensor& T = t->t;
+  const int k = std::max(T.order, 1);
+  double total = std::pow((double)T.n_vars, (double)k);
+  if (total > (double)(1 << 26)) return fail(HOBO_ERR_INVALID_ARG, "N^k exceeds 2^26");
+  int64_t n = (int64_t)total;
+  if (capacity < n) return fail(HOBO_ERR_INVALID_ARG, "capacity smaller than N^k");
+  if (T.integer)
+    std::memset(host_out, 0, (size_t)n * sizeof(int64_t));
+  else
+    std::memset(host_out, 0, (size_t)n * sizeof(double));
+  for (int m = 0; m < T.n_mono(); ++m) {
+    const uint8_t* s = T.mono_idx.data() + T.mono_ptr[(size_t)m];
+    int len = (int)(T.mono_ptr[(size_t)m + 1] - T.mono_ptr[(size_t)m]);
+    // the smallest variable fills the leading k - len + 1 slots (Sec. III.C)
+    int64_t flat = 0;
+    for (int q = 0; q < k; ++q) {
+      int v = q < k - len ? s[0] : s[q - (k - len)];
+      flat = flat * T.n_vars + v;
+    }
+    if (T.integer)
+      static_cast<int64_t*>(host_out)[flat] = T.w_i[(size_t)m];
+    else
+      static_cast<double*>(host_out)[flat] = T.w_f[(size_t)m];
+  }
+  return ok();
+}
+
+hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_mask) {
+  g_err.clear();
+  if (!t) return fail(HOBO_ERR_INVALID_ARG, "tensor is NULL");
+  if (fn_mask & ~7u) return fail(HOBO_ERR_INVALID_ARG, "unknown function bits");
+  if (prec_mask & ~31u) return fail(HOBO_ERR_INVALID_ARG, "unknown precision bits");
+  if (hobo_status s = need_device()) return s;
+  std::string err;
+  for (int p = 0; p <= HOBO_PREC_FP64; ++p) {
+    if (!(prec_mask & (1u << p))) continue;
+    if (p == HOBO_PREC_INT8X4 && !t->t.integer) return fail(HOBO_ERR_PRECISION, "INT8X4 needs an integer tensor");
+    if (p == HOBO_PREC_FP64) {
+      hobo::TermsDev* td;
+      if (int s = hobo::get_terms(&t->t, &td, &err)) return fail(s, err);
+      continue;
+    }
+    hobo::Packed* pk;
+    if (fn_mask & 1u)
+      if (int s = hobo::get_packed(&t->t, hobo::M_ENERGY, p, &pk, &err)) return fail(s, err);
+    if (fn_mask & 2u)
+      if (int s = hobo::get_packed(&t->t, hobo::M_FIELDS, p, &pk, &err)) return fail(s, err);
+    if (fn_mask & 4u)
+      if (int s = hobo::get_packed(&t->t, hobo::M_SLABS, p, &pk, &err)) return fail(s, err);
+  }
+  if (fn_mask & 4u) {
+    hobo::TermsDev* td;
+    if (int s = hobo::get_terms(&t->t, &td, &err)) return fail(s, err);
+  }
+  return ok();
+}
+
+hobo_status hobo_energy(const hobo_tensor* tc, const uint64_t* x_bits, int64_t B, int32_t precision, void* e_out,
+                        void* stream) {
+  g_err.clear();
+  if (hobo_status s = check_bits_args(tc, x_bits, B, precision)) return s;
+  if (!e_out) return fail(HOBO_ERR_INVALID_ARG, "e_out is NULL");
+  if (hobo_status s = need_device()) return s;
+  hobo_tensor* t = const_cast<hobo_tensor*>(tc);
+  std::string err;
+  if (t->t.n_mono() == 0) {
+    size_t bytes = (size_t)B * 8;
+    return hip_status(hipMemsetAsync(e_out, 0, bytes, (hipStream_t)stream), "hipMemsetAsync");
+  }
+  if (precision == HOBO_PREC_FP64) {
+    hobo::TermsDev* td;
+    if (int s = hobo::get_terms(&t->t, &td, &err)) return fail(s, err);
+    hobo::TermArgs a{td, &t->t, x_bits, B, e_out, stream};
+    if (int s = hobo::launch_term_energy(a, &err)) return fail(s, err);
+    return ok();
+  }
+  hobo::Packed* pk;
+  if (int s = hobo::get_packed(&t->t, hobo::M_ENERGY, precision, &pk, &err)) return fail(s, err);
+  int rt, ct;
+  eval_shape(t->t, precision, B, &rt, &ct);
+  size_t wb = hobo::eval_workspace_bytes(&t->t, hobo::M_ENERGY, B, ct);
+  void* work = nullptr;
+  if (wb) {
+    if (hobo_status s = hip_status(hipMallocAsync(&work, wb, (hipStream_t)stream), "hipMallocAsync")) return s;
+  }
+  hobo::EvalArgs a{pk, &t->t, x_bits, B, nullptr, e_out, work, rt, ct, stream};
+  int s = hobo::launch_eval(a, &err);
+  if (work) (void)hipFreeAsync(work, (hipStream_t)stream);
+  if (s) return fail(s, err);
+  return ok();
+}
+
+hobo_status hobo_local_fields(const hobo_tensor* tc, const uint64_t* x_bits, int64_t B, int32_t precision,
+                              void* de_out, void* e_out, void* stream) {
+  g_err.clear();
+  if (hobo_status s = check_bits_args(tc, x_bits, B, precision)) return s;
+  if (!de_out) return fail(HOBO_ERR_INVALID_ARG, "de_out is NULL");
+  if (precision == HOBO_PREC_FP64)
+    return fail(HOBO_ERR_PRECISION, "hobo_local_fields supports FP32, BF16X2, BF16X3 and INT8X4");
+  if (hobo_status s = need_device()) return s;
+  hobo_tensor* t = const_cast<hobo_tensor*>(tc);
+  std::string err;
+  if (t->t.n_mono() == 0) {
+    size_t eb = t->t.integer ? 8 : 4;
+    if (hobo_status s = hip_status(hipMemsetAsync(de_out, 0, (size_t)B * t->t.n_vars * eb, (hipStream_t)stream),
+                                   "hipMemsetAsync"))
+      return s;
+    if (e_out) return hip_status(hipMemsetAsync(e_out, 0, (size_t)B * 8, (hipStream_t)stream), "hipMemsetAsync");
+    return ok();
+  }
+  hobo::Packed* pk;
+  if (int s = hobo::get_packed(&t->t, hobo::M_FIELDS, precision, &pk, &err)) return fail(s, err);
+  int rt, ct;
+  eval_shape(t->t, precision, B, &rt, &ct);
+  size_t wb = e_out ? hobo::eval_workspace_bytes(&t->t, hobo::M_FIELDS, B, ct) : 0;
+  void* work = nullptr;
+  if (wb) {
+    if (hobo_status s = hip_status(hipMallocAsync(&work, wb, (hipStream_t)stream), "hipMallocAsync")) return s;
+  }
+  hobo::EvalArgs a{pk, &t->t, x_bits, B, de_out, e_out, work, rt, ct, stream};
+  int s = hobo::launch_eval(a, &err);
+  if (work) (void)hipFreeAsync(work, (hipStream_t)stream);
+  if (s) return fail(s, err);
+  return ok();
+}
+
+hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, const int64_t* replicas,
+                              const hobo_anneal_params* params, uint64_t* x_inout, uint64_t* best_x_out,
+                              void* best_e_out, double* trace_out, int32_t launch_mode, void* stream) {
+  g_err.clear();
+  if (!tensors || !replicas || !params || !x_inout || !best_x_out || !best_e_out)
+    return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (n_instances < 1) return fail(HOBO_ERR_INVALID_ARG, "n_instances must be >= 1");
+  const hobo_anneal_params& P = *params;
+  if (P.sweeps < 0) return fail(HOBO_ERR_INVALID_ARG, "sweeps must be >= 0");
+  if (!(P.t_start > 0.0) || !(P.t_end > 0.0) || !std::isfinite(P.t_start) || !std::isfinite(P.t_end))
+    return fail(HOBO_ERR_INVALID_ARG, "temperatures must be finite and > 0");
+  if (P.init != HOBO_INIT_RANDOM && P.init != HOBO_INIT_GIVEN) return fail(HOBO_ERR_INVALID_ARG, "unknown init");
+  if (P.proposal != HOBO_PROPOSAL_METROPOLIS && P.proposal != HOBO_PROPOSAL_MASKED)
+    return fail(HOBO_ERR_INVALID_ARG, "unknown proposal");
+  if (P.proposal == HOBO_PROPOSAL_MASKED && !P.attempt)
+    return fail(HOBO_ERR_INVALID_ARG, "MASKED proposal needs attempt masks");
+  if (P.precision < HOBO_PREC_FP32 || P.precision > HOBO_PREC_INT8X4)
+    return fail(HOBO_ERR_PRECISION, "annealing precision must be FP32, BF16X2, BF16X3 or INT8X4");
+  if (launch_mode < HOBO_LAUNCH_PER_INSTANCE || launch_mode > HOBO_LAUNCH_GRAPH)
+    return fail(HOBO_ERR_INVALID_ARG, "unknown launch_mode");
+  if (P.waves_per_block != 0 && P.waves_per_block != 1 && P.waves_per_block != 2 && P.waves_per_block != 4)
+    return fail(HOBO_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2 or 4");
+  bool all_int = true, any_int = false;
+  int max_n = 0;
+  for (int j = 0; j < n_instances; ++j) {
+    if (!tensors[j]) return fail(HOBO_ERR_INVALID_ARG, "tensor is NULL");
+    if (replicas[j] < 1 || replicas[j] > (int64_t)1 << 31) return fail(HOBO_ERR_INVALID_ARG, "replicas out of range");
+    all_int = all_int && tensors[j]->t.integer;
+    any_int = any_int || tensors[j]->t.integer;
+    max_n = std::max(max_n, tensors[j]->t.n_vars);
+  }
+  if (any_int && !all_int) return fail(HOBO_ERR_INVALID_ARG, "instances mix integer and real coefficients");
+  if (P.precision == HOBO_PREC_INT8X4 && !all_int) return fail(HOBO_ERR_PRECISION, "INT8X4 needs integer tensors");
+  if (P.precision == HOBO_PREC_INT8X4 && max_n > 64)
+    return fail(HOBO_ERR_UNSUPPORTED, "INT8X4 annealing supports at most 64 variables");
+  if (hobo_status s = need_device()) return s;
+  hipStream_t st = (hipStream_t)stream;
+  std::string err;
+
+  // device layouts (blocking on first use)
+  std::vector<hobo::Packed*> pks((size_t)n_instances);
+  std::vector<hobo::TermsDev*> tds((size_t)n_instances);
+  for (int j = 0; j < n_instances; ++j) {
+    if (int s = hobo::get_packed(&tensors[j]->t, hobo::M_SLABS, P.precision, &pks[(size_t)j], &err)) return fail(s, err);
+    if (int s = hobo::get_terms(&tensors[j]->t, &tds[(size_t)j], &err)) return fail(s, err);
+  }
+  const int S = P.sweeps;
+  // workspace layout
+  int64_t totB = 0, tot_tiles = 0, max_B = 0;
+  int max_W = 1;
+  for (int j = 0; j < n_instances; ++j) {
+    totB += replicas[j];
+    tot_tiles += (replicas[j] + 15) / 16;
+    max_B = std::max<int64_t>(max_B, replicas[j]);
+    max_W = std::max(max_W, (tensors[j]->t.n_vars + 63) / 64);
+  }
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t off_e = 0;
+  size_t off_best = align(off_e + (size_t)totB * 8);
+  size_t off_trace = align(off_best + (size_t)totB * 8);
+  size_t off_beta = align(off_trace + (size_t)tot_tiles * (size_t)std::max(S, 1) * 8);
+  size_t off_inst = align(off_beta + (size_t)std::max(S, 1) * 8);
+  size_t off_items = align(off_inst + (size_t)n_instances * sizeof(hobo::AnnealInstDev));
+  size_t off_small = align(off_items + (size_t)tot_tiles * sizeof(hobo::AnnealItem));
+  size_t total = align(off_small + (size_t)n_instances * sizeof(hobo::InstSmall));
+
+  // host tables
+  std::vector<double> beta((size_t)std::max(S, 1));
+  for (int s = 0; s < S; ++s) {
+    double T = S == 1 ? P.t_start : P.t_start * std::pow(P.t_end / P.t_start, (double)s / (double)(S - 1));
+    beta[(size_t)s] = 1.0 / T;
+  }
+  // launch shape
+  int ct = 1;
+  for (int j = 0; j < n_instances; ++j) ct = std::max(ct, hobo::anneal_ct_for(tensors[j]->t.n_vars));
+  int nw = P.waves_per_block;
+  if (nw == 0) nw = tot_tiles >= 4 * 1024 ? 4 : (tot_tiles >= 2 * 512 ? 2 : 1);
+
+  // cache lookup
+  std::vector<uint64_t> key;
+  key.push_back((uint64_t)launch_mode);
+  key.push_back((uint64_t)n_instances);
+  for (int j = 0; j < n_instances; ++j) {
+    key.push_back((uint64_t)(uintptr_t)tensors[j]);
+    key.push_back((uint64_t)replicas[j]);
+  }
+  {
+    uint64_t pbits[5];
+    std::memcpy(&pbits[0], &P.t_start, 8);
+    std::memcpy(&pbits[1], &P.t_end, 8);
+    pbits[2] = P.seed;
+    pbits[3] = ((uint64_t)(uint32_t)P.sweeps << 32) | (uint32_t)P.precision;
+    pbits[4] = ((uint64_t)(uint32_t)P.init << 32) | ((uint32_t)P.proposal << 8) | (uint32_t)nw;
+    for (auto v : pbits) key.push_back(v);
+  }
+  key.push_back((uint64_t)(uintptr_t)P.attempt);
+  key.push_back((uint64_t)(uintptr_t)x_inout);
+  key.push_back((uint64_t)(uintptr_t)best_x_out);
+  key.push_back((uint64_t)(uintptr_t)best_e_out);
+  key.push_back((uint64_t)(uintptr_t)trace_out);
+  const int init_random = P.init == HOBO_INIT_RANDOM ? 1 : 0;
+
+  std::lock_guard<std::mutex> lock(g_anneal_mu);
+  AnnealEntry* ent = nullptr;
+  for (auto it = g_anneal.begin(); it != g_anneal.end(); ++it)
+    if (it->key == key) {
+      g_anneal.splice(g_anneal.begin(), g_anneal, it);
+      ent = &g_anneal.front();
+      break;
+    }
+  if (!ent) {
+    AnnealEntry ne;
+    ne.key = key;
+    ne.mode = launch_mode;
+    if (hobo_status hs = hip_status(hipMalloc(&ne.work, total), "hipMalloc")) return hs;
+    char* wb = static_cast<char*>(ne.work);
+    std::vector<hobo::AnnealInstDev> inst((size_t)n_instances);
+    std::vector<hobo::InstSmall> small((size_t)n_instances);
+    std::vector<hobo::AnnealItem> items;
+    ne.item_first.assign((size_t)n_instances + 1, 0);
+    int64_t xoff = 0, roff = 0, toff = 0, att_off = 0;
+    for (int j = 0; j < n_instances; ++j) {
+      const hobo::Tensor& T = tensors[j]->t;
+      const hobo::Packed* pk = pks[(size_t)j];
+      const int64_t Bj = replicas[j];
+      const int W = (T.n_vars + 63) / 64;
+      const int nt = (int)((Bj + 15) / 16);
+      hobo::AnnealInstDev& d = inst[(size_t)j];
+      d.tiles = reinterpret_cast<const unsigned char*>(pk->d_tiles);
+      d.chunks = pk->d_chunks;
+      d.runs = reinterpret_cast<const unsigned long long*>(pk->d_runs);
+      d.slabs = pk->d_slabs;
+      d.x = reinterpret_cast<unsigned long long*>(x_inout + xoff);
+      d.best_x = reinterpret_cast<unsigned long long*>(best_x_out + xoff);
+      d.e_track = reinterpret_cast<double*>(wb + off_e) + roff;
+      d.best_track = reinterpret_cast<double*>(wb + off_best) + roff;
+      d.trace_part = S > 0 ? reinterpret_cast<double*>(wb + off_trace) + toff * S : nullptr;
+      d.attempt = P.proposal == HOBO_PROPOSAL_MASKED ? P.attempt + att_off : nullptr;
+      d.B = Bj;
+      d.n_vars = T.n_vars;
+      d.W = W;
+      d.integer = T.integer ? 1 : 0;
+      d.inst_id = (unsigned long long)j;
+      hobo::InstSmall& sm = small[(size_t)j];
+      sm.rec = tds[(size_t)j]->d_rec;
+      sm.n_mono = tds[(size_t)j]->n_mono;
+      sm.n_vars = T.n_vars;
+      sm.W = W;
+      sm.integer = d.integer;
+      sm.B = Bj;
+      sm.rep_off = roff;
+      sm.x = d.x;
+      sm.best_x = d.best_x;
+      sm.e_track = d.e_track;
+      sm.best_out = all_int ? (void*)(static_cast<int64_t*>(best_e_out) + roff)
+                            : (void*)(static_cast<double*>(best_e_out) + roff);
+      sm.trace_part = d.trace_part;
+      sm.trace_out = trace_out ? trace_out + (int64_t)j * S : nullptr;
+      sm.inst_id = d.inst_id;
+      sm.ntiles16 = nt;
+      ne.item_first[(size_t)j] = (int)items.size();
+      for (int q = 0; q < nt; ++q) items.push_back(hobo::AnnealItem{j, q});
+      xoff += (int64_t)W * Bj;
+      roff += Bj;
+      toff += nt;
+      att_off += (int64_t)nt * S * T.n_vars;
+      int ntj = nt;
+      ne.ct_of.push_back(hobo::anneal_ct_for(T.n_vars));
+      ne.nw_of.push_back(P.waves_per_block ? P.waves_per_block : (ntj >= 4 * 1024 ? 4 : (ntj >= 1024 ? 2 : 1)));
+    }
+    ne.item_first[(size_t)n_instances] = (int)items.size();
+    if (launch_mode != HOBO_LAUNCH_PER_INSTANCE) {
+      // persistent order: most expensive instances first (cost ~ tiles per sweep)
+      std::stable_sort(items.begin(), items.end(), [&](const hobo::AnnealItem& a, const hobo::AnnealItem& b) {
+        return pks[(size_t)a.inst]->ntiles > pks[(size_t)b.inst]->ntiles;
+      });
+    }
+    ne.tb.d_inst = reinterpret_cast<hobo::AnnealInstDev*>(wb + off_inst);
+    ne.tb.d_items = reinterpret_cast<hobo::AnnealItem*>(wb + off_items);
+    ne.tb.d_small = reinterpret_cast<hobo::InstSmall*>(wb + off_small);
+    ne.tb.d_beta = reinterpret_cast<double*>(wb + off_beta);
+    ne.tb.n_items = (int)items.size();
+    ne.tb.max_B = max_B;
+    ne.tb.max_W = max_W;
+    ne.ct = ct;
+    ne.nw = nw;
+    hipError_t e = hipMemcpy(ne.tb.d_inst, inst.data(), inst.size() * sizeof(inst[0]), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(ne.tb.d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(ne.tb.d_small, small.data(), small.size() * sizeof(small[0]), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ne.tb.d_beta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(ne.work);
+      return hip_status(e, "table upload");
+    }
+    if (launch_mode == HOBO_LAUNCH_GRAPH) {
+      hipStream_t cap;
+      if (hobo_status hs = hip_status(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate")) {
+        (void)hipFree(ne.work);
+        return hs;
+      }
+      hipGraph_t graph = nullptr;
+      int s = HOBO_OK;
+      e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        s = hobo::enqueue_anneal_seq(ne.tb, n_instances, S, P.seed, init_random, P.precision, ct, nw, 0,
+                                     ne.tb.n_items, 0, n_instances, (void*)cap, &err);
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e2;
+      }
+      (void)hipStreamDestroy(cap);
+      if (e == hipSuccess && s == HOBO_OK) e = hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess || s != HOBO_OK) {
+        (void)hipFree(ne.work);
+        if (s) return fail(s, err);
+        return hip_status(e, "graph capture");
+      }
+    }
+    g_anneal.push_front(std::move(ne));
+    ent = &g_anneal.front();
+    while (g_anneal.size() > 16) {
+      release_entry(g_anneal.back());
+      g_anneal.pop_back();
+    }
+  }
+  int s = HOBO_OK;
+  if (launch_mode == HOBO_LAUNCH_GRAPH) {
+    return hip_status(hipGraphLaunch(ent->exec, st), "hipGraphLaunch");
+  } else if (launch_mode == HOBO_LAUNCH_PERSISTENT) {
+    s = hobo::enqueue_anneal_seq(ent->tb, n_instances, S, P.seed, init_random, P.precision, ent->ct, ent->nw, 0,
+                                 ent->tb.n_items, 0, n_instances, stream, &err);
+  } else {
+    for (int j = 0; j < n_instances && s == HOBO_OK; ++j) {
+      int i0 = ent->item_first[(size_t)j], ni = ent->item_first[(size_t)j + 1] - i0;
+      s = hobo::enqueue_anneal_seq(ent->tb, n_instances, S, P.seed, init_random, P.precision, ent->ct_of[(size_t)j],
+                                   ent->nw_of[(size_t)j], i0, ni, j, 1, stream, &err);
+    }
+  }
+  if (s) return fail(s, err);
+  return ok();
+}
+
+}  // extern "C"

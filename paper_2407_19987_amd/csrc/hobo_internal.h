@@ -1,0 +1,211 @@
+// Internal declarations shared by the host-side C++ files and the HIP kernels
+// of the HOBO engine.  Nothing here is part of the public C-ABI.
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace hobo {
+
+// ------------------------------------------------------------------ limits
+constexpr int kMaxVars = 256;      // bits of one replica fit in 32 bytes
+constexpr int kMaxOrder = 7;       // a monomial record holds at most 7 variables
+constexpr int kRunWidth = 8;       // variables per run (one byte of bits)
+constexpr int kTileCols = 16;      // MFMA 16x16 output tile width
+
+// precision modes (values match the public header)
+enum Prec : int { P_FP32 = 0, P_BF16X2 = 1, P_BF16X3 = 2, P_INT8X4 = 3, P_FP64 = 4 };
+
+// layouts a coefficient matrix can be packed for
+enum Mode : int { M_FIELDS = 0, M_ENERGY = 1, M_SLABS = 2 };
+
+// runs per chunk: one MFMA K-step covers 4 runs (32 rows) for FP32/BF16 and
+// 8 runs (64 rows) for INT8
+inline int runs_per_chunk(int prec) { return prec == P_INT8X4 ? 8 : 4; }
+// bytes of one 16-column tile of one chunk, all passes / limbs included
+inline int tile_bytes(int prec) {
+  switch (prec) {
+    case P_FP32: return 64 * 8 * 4;
+    case P_BF16X2: return 2 * 64 * 8 * 2;
+    case P_BF16X3: return 3 * 64 * 8 * 2;
+    case P_INT8X4: return 4 * 64 * 16;
+    default: return 0;
+  }
+}
+
+// A run is eight consecutive candidate monomials P u {m}, m = 8*beta .. 8*beta+7,
+// sharing a prefix P (sorted, all < m).  Descriptor bit fields (uint64):
+//   byte 0      beta (block of eight variables)
+//   byte 1      number of prefix variables, or kRunConst / kRunNull
+//   bytes 2..7  prefix variables
+constexpr uint32_t kRunConst = 0xFE;  // constant monomial: only element 0 is 1
+constexpr uint32_t kRunNull = 0xFF;   // padding: every element is 0
+
+struct ChunkMeta {   // one K-step worth of runs (4 or 8)
+  uint32_t tile_off; // offset of the chunk's first tile, in tiles
+  uint8_t t_lo;      // first 16-column tile with a non-zero coefficient
+  uint8_t t_hi;      // one past the last such tile
+  uint8_t seg_end;   // fields layout: all monomials of order <= seg_end are done after this chunk
+  uint8_t pad;
+};
+
+struct SlabMeta {     // annealer: per-variable slab of the local field
+  uint32_t chunk0;    // first chunk of this variable's slab
+  uint32_t nchunks;
+  uint32_t run0;      // first run descriptor (chunk c of the slab uses runs run0 + rpc*c ...)
+  uint32_t pad;
+  double a_f;         // linear coefficient w_{i}
+  int64_t a_i;
+};
+
+// Device-resident packed matrix for one (mode, precision).
+struct Packed {
+  int mode = 0, prec = 0;
+  int nchunks = 0;          // fields/energy: number of chunks
+  int ntiles = 0;           // tiles stored
+  int n_col_tiles = 0;
+  void* d_tiles = nullptr;  // tile_bytes(prec) * ntiles
+  ChunkMeta* d_chunks = nullptr;
+  uint64_t* d_runs = nullptr;
+  SlabMeta* d_slabs = nullptr;  // slabs mode only, [n_vars]
+  std::vector<ChunkMeta> h_chunks;
+  size_t bytes = 0;
+  ~Packed();
+};
+
+// Flat monomial list for the FP64 / int64 term-loop kernels.
+struct TermRec {          // one canonical monomial for the term-loop kernels
+  uint8_t idx[7];         // variables (unused slots repeat idx[0])
+  uint8_t len;
+  union { double f; int64_t i; } w;
+};
+struct TermsDev {
+  int n_mono = 0;
+  TermRec* d_rec = nullptr;
+  size_t bytes = 0;
+  ~TermsDev();
+};
+
+struct Tensor {
+  int n_vars = 0;
+  int order = 0;
+  bool integer = false;
+  int device = 0;
+  // canonical monomials: sorted distinct variables, non-zero weight
+  std::vector<int64_t> mono_ptr;  // [n_mono+1]
+  std::vector<uint8_t> mono_idx;
+  std::vector<int64_t> w_i;  // integer weights (integer instances)
+  std::vector<double> w_f;   // weights as double (both kinds)
+  int64_t offset_i = 0;
+  double offset_f = 0.0;
+  std::vector<int64_t> n_per_order;  // [order+1]
+  double row_norm_max = 0.0;
+  std::vector<double> row_norm;  // ||H_i||_2 over monomials containing i
+
+  std::mutex mu;
+  std::map<int, std::unique_ptr<Packed>> packed;  // key = mode*16 + prec
+  std::unique_ptr<TermsDev> terms;
+  float* d_row_norm = nullptr;
+  ~Tensor();
+  int n_mono() const { return (int)(mono_ptr.size() - 1); }
+};
+
+// ------------------------------------------------------------------ status
+struct Error {
+  int code;
+  std::string msg;
+};
+
+// canon.cpp
+int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term_ptr,
+                 const int32_t* term_idx, const void* coeff, int coeff_type, Tensor* t,
+                 std::string* err);
+
+// pack.cpp -- build (once) the packed layout; returns a status code
+int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err);
+int get_terms(Tensor* t, TermsDev** out, std::string* err);
+
+// kernels.hip -- launchers (return hipError_t as int)
+struct EvalArgs {
+  const Packed* pk;
+  const Tensor* t;
+  const uint64_t* bits;
+  int64_t B;
+  void* de_out;   // fields: [B][N] float or int64 (may be null)
+  void* e_out;    // double[B] or int64[B] (may be null)
+  void* work;     // partial sums [ncg][order][B] (double or int64)
+  int rt, ct;     // tile shape
+  void* stream;
+};
+int launch_eval(const EvalArgs& a, std::string* err);
+size_t eval_workspace_bytes(const Tensor* t, int mode, int64_t B, int ct);
+
+struct TermArgs {
+  const TermsDev* td;
+  const Tensor* t;
+  const uint64_t* bits;
+  int64_t B;
+  void* e_out;  // double or int64
+  void* stream;
+};
+int launch_term_energy(const TermArgs& a, std::string* err);
+
+// ---------------------------------------------------------------- annealer
+struct AnnealInstDev {       // per-instance view of the annealing kernel
+  const unsigned char* tiles;
+  const ChunkMeta* chunks;
+  const unsigned long long* runs;
+  const SlabMeta* slabs;
+  unsigned long long* x;       // [W][B] current states (in/out)
+  unsigned long long* best_x;  // [W][B] best states (out)
+  double* e_track;             // [B] tracked energy (in: start energy, out: final)
+  double* best_track;          // [B] tracked best energy
+  double* trace_part;          // [ntiles16][S] per-tile minima, or null
+  const unsigned char* attempt;  // [ntiles16][S][N] attempt masks, or null
+  long long B;
+  int n_vars, W;
+  int integer;
+  int pad;
+  unsigned long long inst_id;
+};
+struct AnnealItem { int inst; int tile16; };  // 16 replicas of one instance
+
+struct InstSmall {            // per-instance view for the setup / finish kernels
+  const TermRec* rec;
+  int n_mono;
+  int n_vars;
+  int W;
+  int integer;
+  long long B;
+  long long rep_off;
+  unsigned long long* x;
+  unsigned long long* best_x;
+  double* e_track;
+  void* best_out;             // double* or long long*, already offset
+  const double* trace_part;   // [ntiles16][S]
+  double* trace_out;          // [S] or null
+  unsigned long long inst_id;
+  int ntiles16;
+  int pad;
+};
+
+struct AnnealTables {         // device tables of one anneal call
+  AnnealInstDev* d_inst = nullptr;
+  AnnealItem* d_items = nullptr;
+  InstSmall* d_small = nullptr;
+  double* d_beta = nullptr;
+  int n_items = 0;
+  long long max_B = 0;
+  int max_W = 0;
+};
+
+int anneal_ct_for(int n_vars);
+int enqueue_anneal_seq(const AnnealTables& tb, int n_inst, int sweeps, uint64_t seed, int init_random,
+                       int prec, int ct, int nw, int item0, int nitems, int inst0, int ninst,
+                       void* stream, std::string* err);
+
+}  // namespace hobo

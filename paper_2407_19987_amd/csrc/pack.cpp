@@ -1,0 +1,437 @@
+// Device layouts of a canonical HOBO instance.
+//
+// Every contraction in the engine is the product of a generated monomial
+// matrix Y (one row per replica, one column per candidate monomial S' of the
+// replica's bits) with a coefficient matrix M (one row per monomial S', one
+// column per variable c), followed by a per-replica epilogue:
+//
+//   fields  : M[S'][c] = w_{S' u {c}}        (c not in S')    -> g_c, dE_c
+//   energy  : M[S'][c] = w_{S' u {c}}        (c > max S')     -> E = sum_c x_c G_c
+//   slab i  : M[S'][c] = w_{S' u {c} u {i}}  (c > max S', c,S' without i)
+//             -> g_i = w_i + sum_c x_c G_c    (the annealer's field of bit i)
+//
+// The upper-triangular "energy" matrix is the paper's HOBO tensor (Sec. III.C)
+// unfolded along its last index: each monomial S is stored once, at
+// (S minus max S, max S).  A constant row S' = {} carries the linear
+// coefficients.
+//
+// Rows are grouped in *runs*: eight monomials P u {m}, m = 8*beta..8*beta+7,
+// that share a prefix P with max P < m.  A replica's eight values of a run are
+// one byte of its bit vector masked by the product of its prefix bits, so the
+// kernels generate Y from a run descriptor with a byte load.  Runs that are
+// zero in every column are dropped, so sparse instances skip their zeros.
+// Runs are ordered by degree, then block beta, then prefix: in the
+// triangular layouts a run of block beta only reaches columns above 8*beta,
+// so every chunk of runs has a contiguous range of non-zero column tiles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+
+#include "hobo_internal.h"
+#include "../../include/hobo.h"
+
+namespace hobo {
+
+Packed::~Packed() {
+  if (d_tiles) (void)hipFree(d_tiles);
+  if (d_chunks) (void)hipFree(d_chunks);
+  if (d_runs) (void)hipFree(d_runs);
+  if (d_slabs) (void)hipFree(d_slabs);
+}
+TermsDev::~TermsDev() {
+  if (d_rec) (void)hipFree(d_rec);
+}
+Tensor::~Tensor() {
+  packed.clear();
+  terms.reset();
+  if (d_row_norm) (void)hipFree(d_row_norm);
+}
+
+namespace {
+
+// dense coefficient blocks of a run list (8 rows x n columns per run)
+struct RunMat {
+  int n = 0;
+  bool integer = false;
+  std::unordered_map<uint64_t, int> index;
+  std::vector<uint64_t> desc;
+  std::vector<double> cf;  // [run][8][n]
+  std::vector<int64_t> ci;
+
+  int run_of(uint64_t d) {
+    auto it = index.find(d);
+    if (it != index.end()) return it->second;
+    int r = (int)desc.size();
+    index.emplace(d, r);
+    desc.push_back(d);
+    cf.resize(cf.size() + 8 * (size_t)n, 0.0);
+    if (integer) ci.resize(ci.size() + 8 * (size_t)n, 0);
+    return r;
+  }
+  void add(uint64_t d, int e, int c, double wf, int64_t wi) {
+    int r = run_of(d);
+    size_t at = ((size_t)r * 8 + (size_t)e) * (size_t)n + (size_t)c;
+    cf[at] += wf;
+    if (integer) ci[at] += wi;
+  }
+};
+
+inline uint64_t const_desc() { return (uint64_t)kRunConst << 8; }
+inline uint64_t null_desc() { return (uint64_t)kRunNull << 8; }
+// descriptor of the run holding monomial P u {m} (P sorted, all < m)
+inline uint64_t run_desc(const uint8_t* p, int np, int m) {
+  uint64_t d = (uint64_t)(m >> 3) | ((uint64_t)np << 8);
+  for (int j = 0; j < np; ++j) d |= (uint64_t)p[j] << (16 + 8 * j);
+  return d;
+}
+inline int desc_degree(uint64_t d) {
+  uint32_t np = (uint32_t)(d >> 8) & 0xFF;
+  if (np == kRunConst) return 0;
+  if (np == kRunNull) return 99;
+  return (int)np + 1;
+}
+
+// Scatter monomial S' u {c} with weight w into row S' (a run element) and
+// column c.  `rest` = S' sorted (may be empty).
+inline void scatter(RunMat& rm, const uint8_t* rest, int nrest, int c, double wf, int64_t wi) {
+  if (nrest == 0) {
+    rm.add(const_desc(), 0, c, wf, wi);
+  } else {
+    int m = rest[nrest - 1];
+    rm.add(run_desc(rest, nrest - 1, m), m & 7, c, wf, wi);
+  }
+}
+
+// Sorted permutation of the runs: degree, beta, prefix.
+std::vector<int> run_order(const RunMat& rm) {
+  std::vector<int> ord(rm.desc.size());
+  for (size_t r = 0; r < ord.size(); ++r) ord[r] = (int)r;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+    uint64_t da = rm.desc[a], db = rm.desc[b];
+    int ga = desc_degree(da), gb = desc_degree(db);
+    if (ga != gb) return ga < gb;
+    uint32_t ba = (uint32_t)(da & 0xFF), bb = (uint32_t)(db & 0xFF);
+    if (ba != bb) return ba < bb;
+    for (int j = 0; j < 6; ++j) {
+      uint32_t pa = (uint32_t)(da >> (16 + 8 * j)) & 0xFF, pb = (uint32_t)(db >> (16 + 8 * j)) & 0xFF;
+      if (pa != pb) return pa < pb;
+    }
+    return false;
+  });
+  return ord;
+}
+
+inline uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+inline float bf16_to_f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// balanced base-256 digits d_q in [-128, 127], v = sum_q 256^q d_q
+inline bool int8_limbs(int64_t v, int8_t d[4]) {
+  for (int q = 0; q < 4; ++q) {
+    int64_t r = ((v % 256) + 256) % 256;  // 0..255
+    int64_t dq = r >= 128 ? r - 256 : r;
+    d[q] = (int8_t)dq;
+    v = (v - dq) / 256;
+  }
+  return v == 0;
+}
+
+struct PackOut {
+  std::vector<uint8_t> tiles;
+  std::vector<ChunkMeta> chunks;
+  std::vector<uint64_t> runs;
+};
+
+// Append the runs of `rm` (already ordered by `ord`) to `po` as chunks of
+// tiles in precision `prec`.  When `segments` is set the runs of each degree
+// start a new chunk and the chunk that closes a degree carries seg_end.
+int pack_runs(const RunMat& rm, const std::vector<int>& ord, int prec, bool segments, int n_col_tiles,
+              PackOut* po, std::string* err) {
+  const int rpc = runs_per_chunk(prec);
+  const int n = rm.n;
+  // padded run sequence (-1 = null run) and per-run order of its degree
+  std::vector<int> seq;
+  std::vector<int> seg_after;  // order completed after this position (0 = none)
+  for (size_t p = 0; p < ord.size(); ++p) {
+    seq.push_back(ord[p]);
+    int deg = desc_degree(rm.desc[ord[p]]);
+    bool last_of_deg = p + 1 == ord.size() || desc_degree(rm.desc[ord[p + 1]]) != deg;
+    if (segments && last_of_deg) {
+      while (seq.size() % rpc) seq.push_back(-1);
+      seg_after.resize(seq.size(), 0);
+      seg_after.back() = deg + 1;  // runs of degree d are monomials of order d+1
+    }
+  }
+  while (seq.size() % rpc) seq.push_back(-1);
+  seg_after.resize(seq.size(), 0);
+  const int nchunk = (int)(seq.size() / rpc);
+  const int tb = tile_bytes(prec);
+  auto coef_f = [&](int run, int e, int c) -> double {
+    return run < 0 || c >= n ? 0.0 : rm.cf[((size_t)run * 8 + (size_t)e) * (size_t)n + (size_t)c];
+  };
+  auto coef_i = [&](int run, int e, int c) -> int64_t {
+    return run < 0 || c >= n ? 0 : rm.ci[((size_t)run * 8 + (size_t)e) * (size_t)n + (size_t)c];
+  };
+  for (int c = 0; c < nchunk; ++c) {
+    // non-zero column tiles of this chunk
+    int t_lo = n_col_tiles, t_hi = 0;
+    for (int t = 0; t < n_col_tiles; ++t) {
+      bool nz = false;
+      for (int k = 0; k < rpc && !nz; ++k) {
+        int run = seq[(size_t)c * rpc + k];
+        if (run < 0) continue;
+        for (int e = 0; e < 8 && !nz; ++e)
+          for (int j = 0; j < kTileCols && !nz; ++j) nz = coef_f(run, e, 16 * t + j) != 0.0;
+      }
+      if (nz) {
+        t_lo = std::min(t_lo, t);
+        t_hi = std::max(t_hi, t + 1);
+      }
+    }
+    if (t_hi <= t_lo) t_lo = t_hi = 0;
+    ChunkMeta cm{};
+    cm.tile_off = (uint32_t)(po->tiles.size() / (size_t)tb);
+    cm.t_lo = (uint8_t)t_lo;
+    cm.t_hi = (uint8_t)t_hi;
+    cm.seg_end = (uint8_t)seg_after[(size_t)(c + 1) * rpc - 1];
+    po->chunks.push_back(cm);
+    for (int k = 0; k < rpc; ++k) {
+      int run = seq[(size_t)c * rpc + k];
+      po->runs.push_back(run < 0 ? null_desc() : rm.desc[run]);
+    }
+    for (int t = t_lo; t < t_hi; ++t) {
+      size_t base = po->tiles.size();
+      po->tiles.resize(base + (size_t)tb, 0);
+      uint8_t* tile = po->tiles.data() + base;
+      for (int l = 0; l < 64; ++l) {
+        int g = l >> 4, j = l & 15, col = 16 * t + j;
+        if (prec == P_FP32) {
+          float* dst = reinterpret_cast<float*>(tile + l * 32);
+          int run = seq[(size_t)c * rpc + g];
+          for (int e = 0; e < 8; ++e) {
+            double w = rm.integer ? (double)coef_i(run, e, col) : coef_f(run, e, col);
+            dst[e] = (float)w;
+          }
+        } else if (prec == P_BF16X2 || prec == P_BF16X3) {
+          int np = prec == P_BF16X2 ? 2 : 3;
+          int run = seq[(size_t)c * rpc + g];
+          for (int e = 0; e < 8; ++e) {
+            double w = rm.integer ? (double)coef_i(run, e, col) : coef_f(run, e, col);
+            float f = (float)w;
+            uint16_t h[3];
+            h[0] = bf16_rne(f);
+            float r1 = f - bf16_to_f(h[0]);
+            h[1] = bf16_rne(r1);
+            float r2 = r1 - bf16_to_f(h[1]);
+            h[2] = bf16_rne(r2);
+            if (rm.integer) {
+              double back = (double)bf16_to_f(h[0]) + (double)bf16_to_f(h[1]) + (np == 3 ? (double)bf16_to_f(h[2]) : 0.0);
+              if (back != w) {
+                *err = "integer coefficient " + std::to_string((long long)w) + " is not exact in the BF16 split";
+                return HOBO_ERR_RANGE;
+              }
+            }
+            for (int q = 0; q < np; ++q) {
+              uint16_t* dst = reinterpret_cast<uint16_t*>(tile + q * 1024 + l * 16);
+              dst[e] = h[q];
+            }
+          }
+        } else {  // INT8X4
+          for (int e = 0; e < 16; ++e) {
+            int run = seq[(size_t)c * rpc + 2 * g + (e >> 3)];
+            int64_t w = coef_i(run, e & 7, col);
+            int8_t d[4];
+            if (!int8_limbs(w, d)) {
+              *err = "integer coefficient " + std::to_string((long long)w) + " exceeds four INT8 digits";
+              return HOBO_ERR_RANGE;
+            }
+            for (int q = 0; q < 4; ++q) tile[q * 1024 + l * 16 + e] = (uint8_t)d[q];
+          }
+        }
+      }
+    }
+  }
+  return HOBO_OK;
+}
+
+template <class T>
+int upload(const std::vector<T>& v, T** dst, size_t* bytes, std::string* err) {
+  size_t nb = std::max<size_t>(v.size() * sizeof(T), 16);
+  if (hipMalloc(reinterpret_cast<void**>(dst), nb) != hipSuccess) {
+    (void)hipGetLastError();
+    *err = "hipMalloc of " + std::to_string(nb) + " bytes failed";
+    return HOBO_ERR_OOM;
+  }
+  if (!v.empty() && hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    *err = "hipMemcpy to device failed";
+    return HOBO_ERR_HIP;
+  }
+  *bytes += nb;
+  return HOBO_OK;
+}
+
+int check_prec(const Tensor* t, int prec, std::string* err) {
+  if (prec == P_INT8X4 && !t->integer) {
+    *err = "INT8X4 precision needs an integer tensor";
+    return HOBO_ERR_PRECISION;
+  }
+  if (t->integer && (prec == P_FP32 || prec == P_BF16X2 || prec == P_BF16X3)) {
+    // every partial sum of an FP32 accumulation must be an exact integer
+    double s = 0.0;
+    for (auto w : t->w_i) s += std::fabs((double)w);
+    if (s >= 16777216.0) {
+      *err = "integer tensor with sum |w| >= 2^24 cannot be exact in FP32 accumulation; use INT8X4";
+      return HOBO_ERR_RANGE;
+    }
+  }
+  return HOBO_OK;
+}
+
+}  // namespace
+
+int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
+  std::lock_guard<std::mutex> lock(t->mu);
+  int key = mode * 16 + prec;
+  auto it = t->packed.find(key);
+  if (it != t->packed.end()) {
+    *out = it->second.get();
+    return HOBO_OK;
+  }
+  int st = check_prec(t, prec, err);
+  if (st) return st;
+  const int n = t->n_vars;
+  const int n_col_tiles = (n + kTileCols - 1) / kTileCols;
+  const int nm = t->n_mono();
+  std::unique_ptr<Packed> pk(new Packed());
+  pk->mode = mode;
+  pk->prec = prec;
+  pk->n_col_tiles = n_col_tiles;
+  PackOut po;
+  uint8_t rest[kMaxOrder];
+  if (mode == M_FIELDS || mode == M_ENERGY) {
+    RunMat rm;
+    rm.n = n;
+    rm.integer = t->integer;
+    for (int m = 0; m < nm; ++m) {
+      const uint8_t* s = t->mono_idx.data() + t->mono_ptr[m];
+      int len = (int)(t->mono_ptr[m + 1] - t->mono_ptr[m]);
+      double wf = t->w_f[m];
+      int64_t wi = t->integer ? t->w_i[m] : 0;
+      if (mode == M_FIELDS) {
+        for (int a = 0; a < len; ++a) {  // column c = s[a], row S minus c
+          int nr = 0;
+          for (int b = 0; b < len; ++b)
+            if (b != a) rest[nr++] = s[b];
+          scatter(rm, rest, nr, s[a], wf, wi);
+        }
+      } else {  // column c = max S
+        scatter(rm, s, len - 1, s[len - 1], wf, wi);
+      }
+    }
+    st = pack_runs(rm, run_order(rm), prec, mode == M_FIELDS, n_col_tiles, &po, err);
+    if (st) return st;
+    pk->nchunks = (int)po.chunks.size();
+  } else {  // M_SLABS: one triangular matrix per variable i
+    // monomials containing each variable
+    std::vector<std::vector<int>> inc((size_t)n);
+    for (int m = 0; m < nm; ++m)
+      for (int64_t p = t->mono_ptr[m]; p < t->mono_ptr[m + 1]; ++p) inc[t->mono_idx[p]].push_back(m);
+    std::vector<SlabMeta> slabs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+      RunMat rm;
+      rm.n = n;
+      rm.integer = t->integer;
+      SlabMeta sm{};
+      for (int m : inc[(size_t)i]) {
+        const uint8_t* s = t->mono_idx.data() + t->mono_ptr[m];
+        int len = (int)(t->mono_ptr[m + 1] - t->mono_ptr[m]);
+        double wf = t->w_f[m];
+        int64_t wi = t->integer ? t->w_i[m] : 0;
+        if (len == 1) {
+          sm.a_f += wf;
+          sm.a_i += wi;
+          continue;
+        }
+        int nr = 0;
+        uint8_t tt[kMaxOrder];
+        for (int b = 0; b < len; ++b)
+          if (s[b] != i) tt[nr++] = s[b];
+        // slab monomial T = S minus i; column c = max T, row T minus c
+        scatter(rm, tt, nr - 1, tt[nr - 1], wf, wi);
+      }
+      sm.chunk0 = (uint32_t)po.chunks.size();
+      sm.run0 = (uint32_t)po.runs.size();
+      st = pack_runs(rm, run_order(rm), prec, false, n_col_tiles, &po, err);
+      if (st) return st;
+      sm.nchunks = (uint32_t)po.chunks.size() - sm.chunk0;
+      if (sm.nchunks == 0) {  // the annealer visits every slab through at least one chunk
+        ChunkMeta cm{};
+        cm.tile_off = (uint32_t)(po.tiles.size() / (size_t)tile_bytes(prec));
+        po.chunks.push_back(cm);
+        for (int k = 0; k < runs_per_chunk(prec); ++k) po.runs.push_back(null_desc());
+        sm.nchunks = 1;
+      }
+      slabs[(size_t)i] = sm;
+    }
+    pk->nchunks = (int)po.chunks.size();
+    st = upload(slabs, &pk->d_slabs, &pk->bytes, err);
+    if (st) return st;
+  }
+  pk->ntiles = (int)(po.tiles.size() / (size_t)tile_bytes(prec));
+  pk->h_chunks = po.chunks;
+  uint8_t* dt = nullptr;
+  st = upload(po.tiles, &dt, &pk->bytes, err);
+  pk->d_tiles = dt;
+  if (st) return st;
+  st = upload(po.chunks, &pk->d_chunks, &pk->bytes, err);
+  if (st) return st;
+  st = upload(po.runs, &pk->d_runs, &pk->bytes, err);
+  if (st) return st;
+  *out = pk.get();
+  t->packed.emplace(key, std::move(pk));
+  return HOBO_OK;
+}
+
+int get_terms(Tensor* t, TermsDev** out, std::string* err) {
+  std::lock_guard<std::mutex> lock(t->mu);
+  if (t->terms) {
+    *out = t->terms.get();
+    return HOBO_OK;
+  }
+  std::unique_ptr<TermsDev> td(new TermsDev());
+  const int nm = t->n_mono();
+  std::vector<TermRec> rec((size_t)nm);
+  for (int m = 0; m < nm; ++m) {
+    TermRec r{};
+    int len = (int)(t->mono_ptr[m + 1] - t->mono_ptr[m]);
+    const uint8_t* s = t->mono_idx.data() + t->mono_ptr[m];
+    for (int j = 0; j < 7; ++j) r.idx[j] = j < len ? s[j] : s[0];
+    r.len = (uint8_t)len;
+    if (t->integer)
+      r.w.i = t->w_i[m];
+    else
+      r.w.f = t->w_f[m];
+    rec[(size_t)m] = r;
+  }
+  td->n_mono = nm;
+  int st = upload(rec, &td->d_rec, &td->bytes, err);
+  if (st) return st;
+  *out = td.get();
+  t->terms = std::move(td);
+  return HOBO_OK;
+}
+
+}  // namespace hobo

@@ -1,0 +1,245 @@
+"""Python binding of the HOBO engine's C-ABI (include/hobo.h).
+
+Argument marshalling only: every computation runs in libhobo.so's HIP
+kernels.  PyTorch supplies device memory and streams.  Importing this module
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhobo.so")
+
+# status codes
+OK, ERR_INVALID_ARG, ERR_ORDER, ERR_RANGE, ERR_PRECISION, ERR_NO_DEVICE, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = range(9)
+COEFF_INT64, COEFF_F64 = 0, 1
+PREC_FP32, PREC_BF16X2, PREC_BF16X3, PREC_INT8X4, PREC_FP64 = range(5)
+PREC_NAMES = {"fp32": PREC_FP32, "bf16x2": PREC_BF16X2, "bf16x3": PREC_BF16X3, "int8x4": PREC_INT8X4, "fp64": PREC_FP64}
+INIT_RANDOM, INIT_GIVEN = 0, 1
+PROPOSAL_METROPOLIS, PROPOSAL_MASKED = 0, 1
+LAUNCH_PER_INSTANCE, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2
+FN_ENERGY, FN_FIELDS, FN_ANNEAL = 1, 2, 4
+
+EXPORTS = [
+    "hobo_build_tensor", "hobo_free_tensor", "hobo_tensor_info_get", "hobo_tensor_monomials",
+    "hobo_tensor_export_dense", "hobo_tensor_prepare", "hobo_energy", "hobo_local_fields",
+    "hobo_anneal_batch", "hobo_last_error", "hobo_version",
+]
+
+
+class HoboError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hobo status {code}: {msg}")
+        self.code = code
+
+
+class TensorInfo(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("order", ctypes.c_int32), ("is_integer", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_monomials", ctypes.c_int64), ("n_per_order", ctypes.c_int64 * 8),
+                ("offset_i64", ctypes.c_int64), ("offset_f64", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+class AnnealParams(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("precision", ctypes.c_int32), ("t_start", ctypes.c_double),
+                ("t_end", ctypes.c_double), ("seed", ctypes.c_uint64), ("init", ctypes.c_int32),
+                ("proposal", ctypes.c_int32), ("attempt", ctypes.c_void_p), ("waves_per_block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2407_19987_amd.build` first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.hobo_build_tensor.argtypes = [i32, i32, i64, P, P, P, i32, ctypes.POINTER(P), P]
+    lib.hobo_free_tensor.argtypes = [P]
+    lib.hobo_tensor_info_get.argtypes = [P, ctypes.POINTER(TensorInfo)]
+    lib.hobo_tensor_monomials.argtypes = [P, P, i64, P, i64, P, i64]
+    lib.hobo_tensor_export_dense.argtypes = [P, P, i64]
+    lib.hobo_tensor_prepare.argtypes = [P, u32, u32]
+    lib.hobo_energy.argtypes = [P, P, i64, i32, P, P]
+    lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
+    lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
+    for name in EXPORTS:
+        if name in ("hobo_last_error", "hobo_version"):
+            getattr(lib, name).restype = ctypes.c_char_p
+            getattr(lib, name).argtypes = []
+        else:
+            getattr(lib, name).restype = i32
+    return lib
+
+
+lib = _load()
+
+
+def _check(code: int):
+    if code != OK:
+        raise HoboError(code, lib.hobo_last_error().decode())
+
+
+def version() -> str:
+    return lib.hobo_version().decode()
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Tensor:
+    """Owning handle of a compiled HOBO instance (hobo_build_tensor)."""
+
+    def __init__(self, n_vars: int, term_ptr, term_idx, coeff, max_order: int = 0):
+        tp = np.ascontiguousarray(term_ptr, dtype=np.int64)
+        ti = np.ascontiguousarray(term_idx, dtype=np.int32)
+        co = np.asarray(coeff)
+        integer = co.dtype.kind in "iu"
+        co = np.ascontiguousarray(co, dtype=np.int64 if integer else np.float64)
+        h = ctypes.c_void_p()
+        off = np.zeros(1, dtype=np.int64 if integer else np.float64)
+        _check(lib.hobo_build_tensor(int(n_vars), int(max_order), len(co), _np_ptr(tp), _np_ptr(ti), _np_ptr(co),
+                                     COEFF_INT64 if integer else COEFF_F64, ctypes.byref(h), _np_ptr(off)))
+        self._h = h
+        self.integer = integer
+        self.offset = int(off[0]) if integer else float(off[0])
+        info = self.info()
+        self.n_vars = info.n_vars
+        self.order = info.order
+        self.n_monomials = info.n_monomials
+
+    @classmethod
+    def from_terms(cls, terms, max_order: int = 0) -> "Tensor":
+        return cls(terms.n_vars, terms.term_ptr, terms.term_idx, terms.coeff, max_order)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> TensorInfo:
+        inf = TensorInfo()
+        _check(lib.hobo_tensor_info_get(self._h, ctypes.byref(inf)))
+        return inf
+
+    def monomials(self):
+        n = self.info().n_monomials
+        ptr = np.zeros(n + 1, dtype=np.int64)
+        _check(lib.hobo_tensor_monomials(self._h, _np_ptr(ptr), n + 1, None, 0, None, 0))
+        idx = np.zeros(max(int(ptr[-1]), 1), dtype=np.int32)
+        w = np.zeros(max(n, 1), dtype=np.int64 if self.integer else np.float64)
+        _check(lib.hobo_tensor_monomials(self._h, None, 0, _np_ptr(idx), len(idx), _np_ptr(w), len(w)))
+        return ptr, idx[: int(ptr[-1])], w[:n]
+
+    def export_dense(self) -> np.ndarray:
+        k = max(self.order, 1)
+        out = np.zeros(self.n_vars ** k, dtype=np.int64 if self.integer else np.float64)
+        _check(lib.hobo_tensor_export_dense(self._h, _np_ptr(out), out.size))
+        return out.reshape((self.n_vars,) * k)
+
+    def prepare(self, fn_mask: int, prec_mask: int):
+        _check(lib.hobo_tensor_prepare(self._h, fn_mask, prec_mask))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.hobo_free_tensor(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ device calls
+
+
+def _dev_ptr(t) -> int:
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_bits(t: Tensor, x_bits, B: int):
+    w = (t.n_vars + 63) // 64
+    if x_bits.numel() < w * B or x_bits.element_size() != 8:
+        raise ValueError("x_bits must hold [W][B] 64-bit words")
+
+
+def energy(t: Tensor, x_bits, B: int, precision: int, e_out, stream=None):
+    """hobo_energy: e_out (int64 for integer tensors, float64 otherwise) [B]."""
+    _check_bits(t, x_bits, B)
+    if e_out.numel() < B or e_out.element_size() != 8:
+        raise ValueError("e_out must hold B 8-byte values")
+    _check(lib.hobo_energy(t.handle, _dev_ptr(x_bits), int(B), int(precision), _dev_ptr(e_out), _stream(stream)))
+
+
+def local_fields(t: Tensor, x_bits, B: int, precision: int, de_out, e_out=None, stream=None):
+    """hobo_local_fields: de_out [B][N] (int64 for integer tensors, float32 otherwise)."""
+    _check_bits(t, x_bits, B)
+    want = 8 if t.integer else 4
+    if de_out.numel() < B * t.n_vars or de_out.element_size() != want:
+        raise ValueError("de_out has the wrong size or dtype")
+    ep = None
+    if e_out is not None:
+        if e_out.numel() < B or e_out.element_size() != 8:
+            raise ValueError("e_out must hold B 8-byte values")
+        ep = _dev_ptr(e_out)
+    _check(lib.hobo_local_fields(t.handle, _dev_ptr(x_bits), int(B), int(precision), _dev_ptr(de_out), ep,
+                                 _stream(stream)))
+
+
+def anneal_batch(tensors, replicas, x_inout, best_x_out, best_e_out, *, sweeps: int, t_start: float, t_end: float,
+                 seed: int, precision: int = PREC_FP32, init: int = INIT_RANDOM, attempt=None, trace_out=None,
+                 launch_mode: int = LAUNCH_PERSISTENT, waves_per_block: int = 0, stream=None):
+    """hobo_anneal_batch over one or several instances (concatenated buffers)."""
+    if isinstance(tensors, Tensor):
+        tensors = [tensors]
+    n = len(tensors)
+    reps = np.ascontiguousarray(replicas if np.ndim(replicas) else [replicas], dtype=np.int64)
+    if len(reps) != n:
+        raise ValueError("one replica count per tensor")
+    words = sum(((t.n_vars + 63) // 64) * int(b) for t, b in zip(tensors, reps))
+    if x_inout.numel() < words or best_x_out.numel() < words:
+        raise ValueError("bit buffers too small")
+    if best_e_out.numel() < int(reps.sum()) or best_e_out.element_size() != 8:
+        raise ValueError("best_e_out too small")
+    if trace_out is not None and trace_out.numel() < n * sweeps:
+        raise ValueError("trace_out too small")
+    handles = (ctypes.c_void_p * n)(*[t.handle.value for t in tensors])
+    p = AnnealParams()
+    p.sweeps = int(sweeps)
+    p.precision = int(precision)
+    p.t_start = float(t_start)
+    p.t_end = float(t_end)
+    p.seed = int(seed)
+    p.init = int(init)
+    p.proposal = PROPOSAL_MASKED if attempt is not None else PROPOSAL_METROPOLIS
+    p.attempt = _dev_ptr(attempt) if attempt is not None else None
+    p.waves_per_block = int(waves_per_block)
+    _check(lib.hobo_anneal_batch(handles, n, _np_ptr(reps), ctypes.byref(p), _dev_ptr(x_inout), _dev_ptr(best_x_out),
+                                 _dev_ptr(best_e_out), _dev_ptr(trace_out) if trace_out is not None else None,
+                                 int(launch_mode), _stream(stream)))
+
+
+def bits_to_device(bits_np: np.ndarray):
+    """numpy uint64 [W][B] -> torch int64 device tensor with the same bytes."""
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(bits_np, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def bits_to_host(bits_dev) -> np.ndarray:
+    return bits_dev.cpu().numpy().view(np.uint64)

@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU: the library loads and exports every symbol
+of include/hobo.h, the host-side compile step agrees with the oracle's
+independent canonicaliser, the dense export follows the paper's layout, and
+invalid arguments are rejected before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hobo():
+    from paper_2407_19987_amd import hobo as h
+
+    return h
+
+
+def test_library_exports_every_declared_symbol(hobo):
+    with open(os.path.join(ROOT, "include", "hobo.h")) as f:
+        text = f.read()
+    declared = set(re.findall(r"^(?:hobo_status|const char\*)\s+(hobo_\w+)\(", text, flags=re.M))
+    assert declared, "no declarations found"
+    lib = ctypes.CDLL(hobo.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(hobo.EXPORTS)
+
+
+@pytest.mark.parametrize("make", [W.paper_seating, W.paper_pythagorean, W.paper_tsp_intenc,
+                                  lambda: W.cfg_int3(0), lambda: W.cfg_real3(1, n=20), lambda: W.cfg_intenc4(0)])
+def test_canonical_form_matches_oracle(hobo, make):
+    terms = make()
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    assert t.order == c.order and t.n_vars == c.n_vars
+    assert t.offset == c.offset
+    ptr, idx, w = t.monomials()
+    got = {tuple(idx[ptr[m]:ptr[m + 1]].tolist()): (int(w[m]) if t.integer else float(w[m])) for m in range(len(w))}
+    want = dict(zip(c.monos, c.weights))
+    assert got == want
+
+
+@pytest.mark.parametrize("make", [W.paper_tsp_intenc, W.paper_pythagorean, lambda: W.cfg_int3(3, n=9)])
+def test_dense_export_is_paper_layout(hobo, make):
+    terms = make()
+    t = hobo.Tensor.from_terms(terms)
+    np.testing.assert_array_equal(t.export_dense(), oracle.paper_tensor(oracle.canonicalize(terms)))
+
+
+def test_collapse_merge_offset(hobo):
+    p = W.RawPoly([((0, 0, 1), 1), ((1, 0), 2), ((), 3), ((0, 1), -3), ((2,), 5), ((2, 2), -5), ((), -1), ((3, 1, 1), 4)])
+    t = hobo.Tensor.from_terms(W.poly_to_terms(4, p, True))
+    ptr, idx, w = t.monomials()
+    assert t.offset == 2 and t.order == 2
+    assert [tuple(idx[ptr[m]:ptr[m + 1]]) for m in range(len(w))] == [(1, 3)] and list(w) == [4]
+
+
+def _status(hobo, fn):
+    try:
+        fn()
+    except hobo.HoboError as e:
+        return e.code
+    return hobo.OK
+
+
+def test_build_rejects_bad_arguments(hobo):
+    ok = W.cfg_int3(0, n=6)
+    assert _status(hobo, lambda: hobo.Tensor(0, ok.term_ptr, ok.term_idx, ok.coeff)) == hobo.ERR_INVALID_ARG
+    assert _status(hobo, lambda: hobo.Tensor(257, ok.term_ptr, ok.term_idx, ok.coeff)) == hobo.ERR_INVALID_ARG
+    bad_idx = ok.term_idx.copy()
+    bad_idx[3] = 6
+    assert _status(hobo, lambda: hobo.Tensor(6, ok.term_ptr, bad_idx, ok.coeff)) == hobo.ERR_INVALID_ARG
+    bad_ptr = ok.term_ptr.copy()
+    bad_ptr[0] = 1
+    assert _status(hobo, lambda: hobo.Tensor(6, bad_ptr, ok.term_idx, ok.coeff)) == hobo.ERR_INVALID_ARG
+    assert _status(hobo, lambda: hobo.Tensor(6, ok.term_ptr, ok.term_idx, ok.coeff, max_order=2)) == hobo.ERR_ORDER
+    nan = ok.coeff.astype(np.float64)
+    nan[0] = np.nan
+    assert _status(hobo, lambda: hobo.Tensor(6, ok.term_ptr, ok.term_idx, nan)) == hobo.ERR_INVALID_ARG
+    big = W.poly_to_terms(3, W.RawPoly([((0,), 2 ** 62), ((0,), 2 ** 62)]), True)
+    assert _status(hobo, lambda: hobo.Tensor.from_terms(big)) == hobo.ERR_RANGE
+    eight = W.poly_to_terms(9, W.RawPoly([(tuple(range(8)), 1)]), True)
+    assert _status(hobo, lambda: hobo.Tensor.from_terms(eight)) == hobo.ERR_ORDER
+
+
+def test_device_calls_checked_before_gpu(hobo):
+    t = hobo.Tensor.from_terms(W.cfg_real3(0, n=8))
+    lib = hobo.lib
+    # null pointers and bad sizes fail on the host, whatever the device
+    assert lib.hobo_energy(t.handle, None, 4, 0, None, None) == hobo.ERR_INVALID_ARG
+    assert lib.hobo_energy(t.handle, ctypes.c_void_p(16), 0, 0, ctypes.c_void_p(16), None) == hobo.ERR_INVALID_ARG
+    assert lib.hobo_energy(t.handle, ctypes.c_void_p(16), 4, 9, ctypes.c_void_p(16), None) == hobo.ERR_INVALID_ARG
+    assert lib.hobo_energy(t.handle, ctypes.c_void_p(16), 4, hobo.PREC_INT8X4, ctypes.c_void_p(16), None) == hobo.ERR_PRECISION
+    assert lib.hobo_local_fields(t.handle, ctypes.c_void_p(16), 4, hobo.PREC_FP64, ctypes.c_void_p(16), None, None) == hobo.ERR_PRECISION
+    p = hobo.AnnealParams()
+    p.sweeps, p.t_start, p.t_end = 10, 5.0, -1.0
+    reps = np.array([16], dtype=np.int64)
+    hs = (ctypes.c_void_p * 1)(t.handle.value)
+    q = ctypes.c_void_p(16)
+    assert lib.hobo_anneal_batch(hs, 1, reps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), q, q, q, None, 1, None) == hobo.ERR_INVALID_ARG
+    p.t_end = 0.1
+    p.proposal = hobo.PROPOSAL_MASKED
+    assert lib.hobo_anneal_batch(hs, 1, reps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), q, q, q, None, 1, None) == hobo.ERR_INVALID_ARG
+    assert hobo.lib.hobo_last_error().decode() != ""
+
+
+def test_no_device_is_reported_without_gpu(hobo):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    t = hobo.Tensor.from_terms(W.cfg_int3(0, n=6))
+    q = ctypes.c_void_p(16)
+    assert hobo.lib.hobo_energy(t.handle, q, 4, 0, q, None) == hobo.ERR_NO_DEVICE
+    assert hobo.lib.hobo_tensor_prepare(t.handle, 1, 1) == hobo.ERR_NO_DEVICE

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP kernels against the CPU oracle on the same seeded
+inputs.  Integer instances must match bit for bit; real instances within
+|E - E*| <= tol * max(|E*|, s(x)), s(x) = sqrt(sum of squared active terms),
+with tol = 1e-5 (FP32, BF16X3) and 2e-5 (BF16X2, whose coefficients carry a
+2^-18 relative split error)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 1: 2e-5, 2: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2407_19987_amd import hobo
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return hobo, torch
+
+
+def gpu_energy(env, t, bits_np, prec):
+    hobo, torch = env
+    B = bits_np.shape[1]
+    xb = hobo.bits_to_device(bits_np)
+    e = torch.zeros(B, dtype=torch.int64 if t.integer else torch.float64, device="cuda")
+    hobo.energy(t, xb, B, prec, e)
+    torch.cuda.synchronize()
+    return e.cpu().numpy()
+
+
+def gpu_fields(env, t, bits_np, prec, want_e=True):
+    hobo, torch = env
+    B = bits_np.shape[1]
+    xb = hobo.bits_to_device(bits_np)
+    de = torch.zeros((B, t.n_vars), dtype=torch.int64 if t.integer else torch.float32, device="cuda")
+    e = torch.zeros(B, dtype=torch.int64 if t.integer else torch.float64, device="cuda") if want_e else None
+    hobo.local_fields(t, xb, B, prec, de, e)
+    torch.cuda.synchronize()
+    return de.cpu().numpy(), (e.cpu().numpy() if want_e else None)
+
+
+INT_PRECS = [0, 1, 2, 3]
+REAL_PRECS = [0, 1, 2]
+
+
+def _int_instance(seed, n, k, lo=-6, hi=6, dens=0.8):
+    rng = np.random.default_rng(seed)
+    subs, co = [], []
+    for r in range(1, k + 1):
+        s = W.lex_subsets(n, r)
+        keep = rng.random(len(s)) < dens
+        subs.append(s[keep])
+        co.append(rng.integers(lo, hi + 1, size=int(keep.sum())))
+    return W.subsets_to_terms(n, subs, co, True)
+
+
+# ------------------------------------------------------------ integer instances, bit-exact
+
+
+@pytest.mark.parametrize("prec", INT_PRECS + [4])
+def test_int3_n16_energy_all_states(env, prec):
+    hobo, _ = env
+    terms = W.cfg_int3(seed=0)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.all_states(16))
+    got = gpu_energy(env, t, bits, prec)
+    want = oracle.energy(c, bits)
+    np.testing.assert_array_equal(got, want)
+    # exhaustive minimum agrees with the oracle's Gray-code search
+    best, nmin, args = oracle.brute_force(c, cap=4096)
+    assert got.min() == best
+    assert sorted(np.nonzero(got == best)[0].tolist()) == sorted(args)
+
+
+@pytest.mark.parametrize("prec", INT_PRECS)
+@pytest.mark.parametrize("B", [1, 17, 1024])
+def test_int3_n16_fields_random_states(env, prec, B):
+    hobo, _ = env
+    terms = W.cfg_int3(seed=1)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(16, B, seed=1000 + B))
+    de, e = gpu_fields(env, t, bits, prec)
+    g_ref, de_ref = oracle.fields(c, bits)
+    np.testing.assert_array_equal(de, de_ref)
+    np.testing.assert_array_equal(e, oracle.energy(c, bits))
+
+
+@pytest.mark.parametrize("make,nv", [(W.paper_seating, 25), (W.paper_pythagorean, 12), (W.paper_tsp_intenc, 6)])
+@pytest.mark.parametrize("prec", [0, 3])
+def test_paper_problems(env, golden, make, nv, prec):
+    hobo, _ = env
+    terms = make()
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    if nv <= 16:
+        x = W.all_states(nv)
+    else:
+        x = W.random_states(nv, 4096, seed=3)
+        grids = golden["seating"]["printed_optima_grids"]
+        x = np.concatenate([x, np.array(grids, dtype=np.uint8).reshape(len(grids), -1)])
+    bits = W.pack_bits(x)
+    np.testing.assert_array_equal(gpu_energy(env, t, bits, prec), oracle.energy(c, bits))
+    de, e = gpu_fields(env, t, bits, prec)
+    np.testing.assert_array_equal(de, oracle.fields(c, bits)[1])
+    np.testing.assert_array_equal(e, oracle.energy(c, bits))
+
+
+@pytest.mark.parametrize("n,k", [(7, 2), (25, 3), (37, 4), (70, 3), (150, 2), (200, 3)])
+@pytest.mark.parametrize("prec", [0, 3])
+def test_ragged_sizes(env, n, k, prec):
+    """N not a multiple of 16 or 64, several column tiles, W up to 4 words."""
+    hobo, _ = env
+    terms = _int_instance(n * 10 + k, n, k, dens=0.5 if n < 100 else 0.15, lo=-3, hi=3)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(n, 97, seed=n))
+    np.testing.assert_array_equal(gpu_energy(env, t, bits, prec), oracle.energy(c, bits))
+    de, e = gpu_fields(env, t, bits, prec)
+    np.testing.assert_array_equal(de, oracle.fields(c, bits)[1])
+    np.testing.assert_array_equal(e, oracle.energy(c, bits))
+
+
+def test_intenc4_int8_bit_exact(env):
+    """Integer-encoded order 4 (coefficients up to ~2^25): only INT8X4 is exact."""
+    hobo, _ = env
+    terms = W.cfg_intenc4(seed=0)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    assert t.order == 4 and t.n_vars == 48
+    bits = W.pack_bits(W.random_states(48, 512, seed=7))
+    np.testing.assert_array_equal(gpu_energy(env, t, bits, 3), oracle.energy(c, bits))
+    de, e = gpu_fields(env, t, bits, 3)
+    np.testing.assert_array_equal(de, oracle.fields(c, bits)[1])
+    np.testing.assert_array_equal(e, oracle.energy(c, bits))
+    # FP32 accumulation cannot be exact here and is refused
+    with pytest.raises(hobo.HoboError) as ei:
+        gpu_energy(env, t, bits, 0)
+    assert ei.value.code == hobo.ERR_RANGE
+
+
+def test_degenerate_instances(env):
+    hobo, torch = env
+    # no monomials at all (constant only)
+    t = hobo.Tensor.from_terms(W.poly_to_terms(5, W.RawPoly.const(7), True))
+    assert t.offset == 7 and t.n_monomials == 0
+    bits = W.pack_bits(W.random_states(5, 33, seed=1))
+    assert (gpu_energy(env, t, bits, 0) == 0).all()
+    de, e = gpu_fields(env, t, bits, 0)
+    assert (de == 0).all() and (e == 0).all()
+    # linear only
+    terms = W.poly_to_terms(9, sum((W.RawPoly.var(i) * (i - 4) for i in range(9)), W.RawPoly()), True)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(9, 50, seed=2))
+    for prec in (0, 1, 3):
+        np.testing.assert_array_equal(gpu_energy(env, t, bits, prec), oracle.energy(c, bits))
+        de, e = gpu_fields(env, t, bits, prec)
+        np.testing.assert_array_equal(de, oracle.fields(c, bits)[1])
+
+
+# ------------------------------------------------------------ real instances, tolerance
+
+
+def _rel_err(got, want, scale):
+    return np.abs(got - want) / np.maximum(np.abs(want), scale)
+
+
+@pytest.mark.parametrize("prec", REAL_PRECS)
+def test_real3_n128_energy_and_fields(env, prec):
+    hobo, _ = env
+    terms = W.cfg_real3(seed=0)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(128, 160, seed=11))
+    want = oracle.energy(c, bits)
+    scale = oracle.active_scale(c, bits)
+    got = gpu_energy(env, t, bits, prec)
+    assert _rel_err(got, want, scale).max() <= TOL[prec]
+    de, e = gpu_fields(env, t, bits, prec)
+    assert _rel_err(e, want, scale).max() <= TOL[prec]
+    _, de_ref = oracle.fields(c, bits)
+    fscale = oracle.field_scale(c, bits)
+    assert _rel_err(de.astype(np.float64), de_ref, fscale).max() <= TOL[prec]
+
+
+def test_real3_fp64_rescore(env):
+    hobo, _ = env
+    terms = W.cfg_real3(seed=2, n=64)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(64, 300, seed=5))
+    got = gpu_energy(env, t, bits, 4)
+    want = oracle.energy(c, bits)
+    scale = oracle.active_scale(c, bits)
+    assert _rel_err(got, want, scale).max() <= 1e-12
+
+
+@pytest.mark.parametrize("prec", REAL_PRECS)
+def test_real3_full_batch_sampled(env, prec):
+    """Full 4096-replica batch in the benchmark's launch shape; the oracle
+    checks a sample of 64 rows and the rest must satisfy Euler's identity
+    between the two kernels (energy kernel vs fields-derived energy)."""
+    hobo, _ = env
+    terms = W.cfg_real3(seed=1)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    x = W.random_states(128, 4096, seed=12)
+    bits = W.pack_bits(x)
+    e_gpu = gpu_energy(env, t, bits, prec)
+    de, e_f = gpu_fields(env, t, bits, prec)
+    rows = np.random.default_rng(0).choice(4096, size=64, replace=False)
+    sub = W.pack_bits(x[rows])
+    want = oracle.energy(c, sub)
+    scale = oracle.active_scale(c, sub)
+    assert _rel_err(e_gpu[rows], want, scale).max() <= TOL[prec]
+    _, de_ref = oracle.fields(c, sub)
+    fscale = oracle.field_scale(c, sub)
+    assert _rel_err(de[rows].astype(np.float64), de_ref, fscale).max() <= TOL[prec]
+    # every row: the two kernels agree to the same criterion, with the sampled
+    # rows' median active scale as the floor
+    floor = float(np.median(scale))
+    assert np.max(np.abs(e_gpu - e_f) / np.maximum(np.abs(e_gpu), floor)) <= 2 * TOL[prec]
