@@ -172,7 +172,8 @@ typedef struct {
   int32_t proposal;    /* HOBO_PROPOSAL_METROPOLIS, or MASKED with attempt masks */
   const uint8_t* attempt; /* MASKED: device uint8 [ceil(B/16)][S][N] per instance,
                              concatenated; 1 = the 16-replica group visits the bit */
-  int32_t waves_per_block; /* 0 = tuned default */
+  int32_t waves_per_block; /* waves sharing 16 replicas (1, 2, 4, 8; they split the
+                              columns); 0 = default.  Results do not depend on it. */
   int32_t reserved;
 } hobo_anneal_params;
 
@@ -206,6 +207,16 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances,
                               const int64_t* replicas, const hobo_anneal_params* params,
                               uint64_t* x_inout, uint64_t* best_x_out, void* best_e_out,
                               double* trace_out, int32_t launch_mode, void* stream);
+
+/* ------------------------------------------------------------- timing */
+/* Kernel timing for measurement tools.  While enabled, each launch of the
+ * annealing kernel (id 0), the fields kernel (id 1) and the energy kernel
+ * (id 2) is bracketed by two HIP events recorded on the caller's stream
+ * (not during stream capture).  hobo_timing_read waits for the recorded
+ * launches of one kernel, returns their summed duration in milliseconds and
+ * their count, and releases them. */
+hobo_status hobo_timing_enable(int32_t enable);
+hobo_status hobo_timing_read(int32_t kernel, double* total_ms, int64_t* launches);
 
 /* Description of the last error on the calling thread ("" if none). */
 const char* hobo_last_error(void);

@@ -108,6 +108,20 @@ void release_entry(AnnealEntry& e) {
 extern "C" {
 
 const char* hobo_last_error(void) { return g_err.c_str(); }
+
+hobo_status hobo_timing_enable(int32_t enable) {
+  g_err.clear();
+  hobo::timing_enable(enable);
+  return ok();
+}
+
+hobo_status hobo_timing_read(int32_t kernel, double* total_ms, int64_t* launches) {
+  g_err.clear();
+  if (!total_ms || !launches) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (kernel < 0 || kernel > 2) return fail(HOBO_ERR_INVALID_ARG, "kernel id must be 0, 1 or 2");
+  if (int s = hobo::timing_read(kernel, total_ms, launches)) return fail(s, "event timing failed");
+  return ok();
+}
 const char* hobo_version(void) { return "hobo-mi355x 0.1 (gfx950)"; }
 
 hobo_status hobo_build_tensor(int32_t n_vars, int32_t max_order, int64_t n_terms, const int64_t* term_ptr,
@@ -304,8 +318,14 @@ hobo_status hobo_energy(const hobo_tensor* tc, const uint64_t* x_bits, int64_t B
   if (precision == HOBO_PREC_FP64) {
     hobo::TermsDev* td;
     if (int s = hobo::get_terms(&t->t, &td, &err)) return fail(s, err);
-    hobo::TermArgs a{td, &t->t, x_bits, B, e_out, stream};
-    if (int s = hobo::launch_term_energy(a, &err)) return fail(s, err);
+    void* work = nullptr;
+    if (hobo_status s = hip_status(hipMallocAsync(&work, hobo::term_workspace_bytes(&t->t, B), (hipStream_t)stream),
+                                   "hipMallocAsync"))
+      return s;
+    hobo::TermArgs a{td, &t->t, x_bits, B, e_out, work, stream};
+    int s = hobo::launch_term_energy(a, &err);
+    (void)hipFreeAsync(work, (hipStream_t)stream);
+    if (s) return fail(s, err);
     return ok();
   }
   hobo::Packed* pk;
@@ -378,8 +398,9 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     return fail(HOBO_ERR_PRECISION, "annealing precision must be FP32, BF16X2, BF16X3 or INT8X4");
   if (launch_mode < HOBO_LAUNCH_PER_INSTANCE || launch_mode > HOBO_LAUNCH_GRAPH)
     return fail(HOBO_ERR_INVALID_ARG, "unknown launch_mode");
-  if (P.waves_per_block != 0 && P.waves_per_block != 1 && P.waves_per_block != 2 && P.waves_per_block != 4)
-    return fail(HOBO_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2 or 4");
+  if (P.waves_per_block != 0 && P.waves_per_block != 1 && P.waves_per_block != 2 && P.waves_per_block != 4 &&
+      P.waves_per_block != 8)
+    return fail(HOBO_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
   bool all_int = true, any_int = false;
   int max_n = 0;
   for (int j = 0; j < n_instances; ++j) {
@@ -422,7 +443,15 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   size_t off_inst = align(off_beta + (size_t)std::max(S, 1) * 8);
   size_t off_items = align(off_inst + (size_t)n_instances * sizeof(hobo::AnnealInstDev));
   size_t off_small = align(off_items + (size_t)tot_tiles * sizeof(hobo::AnnealItem));
-  size_t total = align(off_small + (size_t)n_instances * sizeof(hobo::InstSmall));
+  size_t off_term = align(off_small + (size_t)n_instances * sizeof(hobo::InstSmall));
+  size_t term_bytes = 0;
+  int max_groups = 1;
+  for (int j = 0; j < n_instances; ++j) {
+    term_bytes += align(hobo::term_workspace_bytes(&tensors[j]->t, replicas[j]));
+    max_groups = std::max(max_groups, (tds[(size_t)j]->n_mono + 4095) / 4096);
+  }
+  size_t off_ones = align(off_term + term_bytes);
+  size_t total = align(off_ones + 256);
 
   // host tables
   std::vector<double> beta((size_t)std::max(S, 1));
@@ -431,10 +460,10 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     beta[(size_t)s] = 1.0 / T;
   }
   // launch shape
-  int ct = 1;
-  for (int j = 0; j < n_instances; ++j) ct = std::max(ct, hobo::anneal_ct_for(tensors[j]->t.n_vars));
-  int nw = P.waves_per_block;
-  if (nw == 0) nw = tot_tiles >= 4 * 1024 ? 4 : (tot_tiles >= 2 * 512 ? 2 : 1);
+  int ct = 1, nw = 1;  // column tiles per wave, waves per work-group
+  int maxT = 1;
+  for (int j = 0; j < n_instances; ++j) maxT = std::max(maxT, (tensors[j]->t.n_vars + 15) / 16);
+  hobo::anneal_shape(maxT, P.waves_per_block, &ct, &nw);
 
   // cache lookup
   std::vector<uint64_t> key;
@@ -479,6 +508,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     std::vector<hobo::AnnealItem> items;
     ne.item_first.assign((size_t)n_instances + 1, 0);
     int64_t xoff = 0, roff = 0, toff = 0, att_off = 0;
+    size_t term_off = 0;
     for (int j = 0; j < n_instances; ++j) {
       const hobo::Tensor& T = tensors[j]->t;
       const hobo::Packed* pk = pks[(size_t)j];
@@ -518,15 +548,20 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       sm.trace_out = trace_out ? trace_out + (int64_t)j * S : nullptr;
       sm.inst_id = d.inst_id;
       sm.ntiles16 = nt;
+      sm.term_part = wb + off_term + term_off;
+      term_off += align(hobo::term_workspace_bytes(&T, Bj));
       ne.item_first[(size_t)j] = (int)items.size();
       for (int q = 0; q < nt; ++q) items.push_back(hobo::AnnealItem{j, q});
       xoff += (int64_t)W * Bj;
       roff += Bj;
       toff += nt;
       att_off += (int64_t)nt * S * T.n_vars;
-      int ntj = nt;
-      ne.ct_of.push_back(hobo::anneal_ct_for(T.n_vars));
-      ne.nw_of.push_back(P.waves_per_block ? P.waves_per_block : (ntj >= 4 * 1024 ? 4 : (ntj >= 1024 ? 2 : 1)));
+      int ctj, nwj;
+      hobo::anneal_shape((T.n_vars + 15) / 16, P.waves_per_block, &ctj, &nwj);
+      ne.ct_of.push_back(ctj);
+      ne.nw_of.push_back(nwj);
+      d.n_chunks = pk->nchunks;
+      d.n_tiles = (unsigned)pk->ntiles;
     }
     ne.item_first[(size_t)n_instances] = (int)items.size();
     if (launch_mode != HOBO_LAUNCH_PER_INSTANCE) {
@@ -542,6 +577,8 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     ne.tb.n_items = (int)items.size();
     ne.tb.max_B = max_B;
     ne.tb.max_W = max_W;
+    ne.tb.max_groups = max_groups;
+    ne.tb.d_ones = reinterpret_cast<const unsigned char*>(wb + off_ones);
     ne.ct = ct;
     ne.nw = nw;
     hipError_t e = hipMemcpy(ne.tb.d_inst, inst.data(), inst.size() * sizeof(inst[0]), hipMemcpyHostToDevice);
@@ -550,6 +587,10 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     if (e == hipSuccess)
       e = hipMemcpy(ne.tb.d_small, small.data(), small.size() * sizeof(small[0]), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ne.tb.d_beta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      std::vector<unsigned char> ones(256, 1);
+      e = hipMemcpy(wb + off_ones, ones.data(), ones.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
       (void)hipFree(ne.work);
       return hip_status(e, "table upload");

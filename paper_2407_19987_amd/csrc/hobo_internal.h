@@ -49,8 +49,9 @@ struct ChunkMeta {   // one K-step worth of runs (4 or 8)
   uint32_t tile_off; // offset of the chunk's first tile, in tiles
   uint8_t t_lo;      // first 16-column tile with a non-zero coefficient
   uint8_t t_hi;      // one past the last such tile
-  uint8_t seg_end;   // fields layout: all monomials of order <= seg_end are done after this chunk
-  uint8_t pad;
+  uint8_t seg_end;   // fields layout: all monomials of order <= seg_end are done after this chunk;
+                     // slab layout: 1 on the last chunk of a variable's slab
+  uint8_t bit;       // slab layout: the variable whose slab holds this chunk
 };
 
 struct SlabMeta {     // annealer: per-variable slab of the local field
@@ -150,9 +151,11 @@ struct TermArgs {
   const uint64_t* bits;
   int64_t B;
   void* e_out;  // double or int64
+  void* work;   // term_workspace_bytes
   void* stream;
 };
 int launch_term_energy(const TermArgs& a, std::string* err);
+size_t term_workspace_bytes(const Tensor* t, int64_t B);
 
 // ---------------------------------------------------------------- annealer
 struct AnnealInstDev {       // per-instance view of the annealing kernel
@@ -169,8 +172,10 @@ struct AnnealInstDev {       // per-instance view of the annealing kernel
   long long B;
   int n_vars, W;
   int integer;
-  int pad;
+  int n_chunks;                // chunks of all slabs (one sweep)
   unsigned long long inst_id;
+  unsigned n_tiles;            // tiles stored in the packed buffer
+  unsigned pad2;
 };
 struct AnnealItem { int inst; int tile16; };  // 16 replicas of one instance
 
@@ -191,6 +196,7 @@ struct InstSmall {            // per-instance view for the setup / finish kernel
   unsigned long long inst_id;
   int ntiles16;
   int pad;
+  void* term_part;            // [term groups][B] partial sums of the term-loop energies
 };
 
 struct AnnealTables {         // device tables of one anneal call
@@ -198,12 +204,19 @@ struct AnnealTables {         // device tables of one anneal call
   AnnealItem* d_items = nullptr;
   InstSmall* d_small = nullptr;
   double* d_beta = nullptr;
+  const unsigned char* d_ones = nullptr;  // one byte equal to 1
   int n_items = 0;
   long long max_B = 0;
   int max_W = 0;
+  int max_groups = 1;         // term-loop groups of the largest instance
 };
 
-int anneal_ct_for(int n_vars);
+// (column tiles per wave, waves per work-group) of the annealer for T column tiles
+void anneal_shape(int T, int cs_req, int* ctw, int* cs);
+
+// launch timing (kernels: 0 = annealer, 1 = fields, 2 = energy)
+void timing_enable(int on);
+int timing_read(int kernel, double* total_ms, int64_t* launches);
 int enqueue_anneal_seq(const AnnealTables& tb, int n_inst, int sweeps, uint64_t seed, int init_random,
                        int prec, int ct, int nw, int item0, int nitems, int inst0, int ninst,
                        void* stream, std::string* err);

@@ -320,6 +320,9 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
   pk->prec = prec;
   pk->n_col_tiles = n_col_tiles;
   PackOut po;
+  // tile 0 is all zeros: the kernels load it in place of absent tiles so that
+  // every chunk issues the same number of loads
+  po.tiles.assign((size_t)tile_bytes(prec), 0);
   uint8_t rest[kMaxOrder];
   if (mode == M_FIELDS || mode == M_ENERGY) {
     RunMat rm;
@@ -383,6 +386,10 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
         po.chunks.push_back(cm);
         for (int k = 0; k < runs_per_chunk(prec); ++k) po.runs.push_back(null_desc());
         sm.nchunks = 1;
+      }
+      for (uint32_t c = sm.chunk0; c < sm.chunk0 + sm.nchunks; ++c) {
+        po.chunks[c].bit = (uint8_t)i;
+        po.chunks[c].seg_end = c + 1 == sm.chunk0 + sm.nchunks ? 1 : 0;
       }
       slabs[(size_t)i] = sm;
     }

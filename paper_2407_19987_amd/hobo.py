@@ -27,7 +27,7 @@ FN_ENERGY, FN_FIELDS, FN_ANNEAL = 1, 2, 4
 EXPORTS = [
     "hobo_build_tensor", "hobo_free_tensor", "hobo_tensor_info_get", "hobo_tensor_monomials",
     "hobo_tensor_export_dense", "hobo_tensor_prepare", "hobo_energy", "hobo_local_fields",
-    "hobo_anneal_batch", "hobo_last_error", "hobo_version",
+    "hobo_anneal_batch", "hobo_timing_enable", "hobo_timing_read", "hobo_last_error", "hobo_version",
 ]
 
 
@@ -64,6 +64,8 @@ def _load():
     lib.hobo_energy.argtypes = [P, P, i64, i32, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
+    lib.hobo_timing_enable.argtypes = [i32]
+    lib.hobo_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
         if name in ("hobo_last_error", "hobo_version"):
             getattr(lib, name).restype = ctypes.c_char_p
@@ -232,6 +234,21 @@ def anneal_batch(tensors, replicas, x_inout, best_x_out, best_e_out, *, sweeps: 
     _check(lib.hobo_anneal_batch(handles, n, _np_ptr(reps), ctypes.byref(p), _dev_ptr(x_inout), _dev_ptr(best_x_out),
                                  _dev_ptr(best_e_out), _dev_ptr(trace_out) if trace_out is not None else None,
                                  int(launch_mode), _stream(stream)))
+
+
+KERNEL_ANNEAL, KERNEL_FIELDS, KERNEL_ENERGY = 0, 1, 2
+
+
+def timing_enable(on: bool = True):
+    _check(lib.hobo_timing_enable(1 if on else 0))
+
+
+def timing_read(kernel: int):
+    """(total milliseconds, launches) of the timed launches of one kernel."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib.hobo_timing_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def bits_to_device(bits_np: np.ndarray):

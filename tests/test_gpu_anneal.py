@@ -94,6 +94,19 @@ def test_trajectory_identity_instances(env, make, prec):
     assert_same(g, o)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_trajectory_identity_long_chunk_list(env, prec):
+    """An order-4 instance on 64 variables: its slabs hold thousands of
+    chunks, so the chunk metadata is restaged in LDS while the stream runs."""
+    hobo, _ = env
+    terms = _int_instance(12, 64, 4, lo=-3, hi=3, dens=0.3)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    g = run_gpu(env, t, 40, 6, 4.0, 0.5, seed=17, prec=prec)[0]
+    o = oracle.anneal(c, 40, 6, 4.0, 0.5, seed=17)
+    assert_same(g, o)
+
+
 def test_paper_minima_reached(env, golden):
     hobo, _ = env
     for make, key, prec in ((W.paper_seating, "seating", 0), (W.paper_pythagorean, "pythagorean", 3),
