@@ -349,3 +349,39 @@ def decode_int(bits_row: np.ndarray, first_var: int, n_bits: int, msb_first: boo
         b = int(bits_row[first_var + a])
         v += b << ((n_bits - 1 - a) if msb_first else a)
     return v
+
+
+# --------------------------------------------------------------------------
+# flip-proposal network: initial weights
+# --------------------------------------------------------------------------
+
+MLP_HIDDEN = 256
+MLP_FEATURES = 3
+MLP_PARAMS = MLP_FEATURES * MLP_HIDDEN + 2 * MLP_HIDDEN + 1
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """FP32 parameter vector of the 3 -> 256 -> 1 proposal network, Glorot
+    uniform matrices and zero biases: W1[f][u] at f*256+u, b1 at 768, W2 at
+    1024, b2 at 1280."""
+    rng = np.random.default_rng(seed)
+    a1 = np.sqrt(6.0 / (MLP_FEATURES + MLP_HIDDEN))
+    a2 = np.sqrt(6.0 / (MLP_HIDDEN + 1))
+    p = np.zeros(MLP_PARAMS, dtype=np.float32)
+    p[:MLP_FEATURES * MLP_HIDDEN] = rng.uniform(-a1, a1, MLP_FEATURES * MLP_HIDDEN)
+    p[MLP_FEATURES * MLP_HIDDEN + MLP_HIDDEN:MLP_FEATURES * MLP_HIDDEN + 2 * MLP_HIDDEN] = rng.uniform(-a2, a2,
+                                                                                                     MLP_HIDDEN)
+    return p
+
+
+def mlp_samples(m: int, seed: int, p_pos: float = 0.3) -> tuple[np.ndarray, np.ndarray]:
+    """Synthetic (features [m][3] FP32, labels [m] FP32) with the value ranges
+    of recorded transitions: x in {0,1}, beta*dE ~ N(0, 3^2), beta*||H|| in
+    [0.1, 20]; labels Bernoulli(p_pos)."""
+    rng = np.random.default_rng(seed)
+    f = np.zeros((m, MLP_FEATURES), dtype=np.float32)
+    f[:, 0] = rng.integers(0, 2, m)
+    f[:, 1] = rng.normal(0.0, 3.0, m)
+    f[:, 2] = rng.uniform(0.1, 20.0, m)
+    y = (rng.random(m) < p_pos).astype(np.float32)
+    return f, y
