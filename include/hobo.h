@@ -159,36 +159,56 @@ hobo_status hobo_local_fields(const hobo_tensor* t, const uint64_t* x_bits, int6
 
 /* ------------------------------------------------------------- annealing */
 enum { HOBO_INIT_RANDOM = 0, HOBO_INIT_GIVEN = 1 };
-enum { HOBO_PROPOSAL_METROPOLIS = 0, HOBO_PROPOSAL_MASKED = 1 };
+enum { HOBO_PROPOSAL_METROPOLIS = 0, HOBO_PROPOSAL_MASKED = 1, HOBO_PROPOSAL_LEARNED = 2 };
 enum { HOBO_LAUNCH_PER_INSTANCE = 0, HOBO_LAUNCH_PERSISTENT = 1, HOBO_LAUNCH_GRAPH = 2 };
+/* annealing kernels: AUTO picks BLOCKS where it applies (order <= 3, FP32 /
+ * BF16X2 / BF16X3), else SLABS.  Both run the same chain. */
+enum { HOBO_ANNEAL_AUTO = 0, HOBO_ANNEAL_SLABS = 1, HOBO_ANNEAL_BLOCKS = 2 };
 
 typedef struct {
-  int32_t sweeps;      /* S >= 0 */
+  int32_t sweeps;      /* sweeps of this call, >= 0 */
   int32_t precision;   /* FP32 | BF16X2 | BF16X3 | INT8X4 */
   double t_start;      /* T_0 > 0 */
-  double t_end;        /* T_{S-1} > 0; T_s = T_0 (T_end/T_0)^(s/(S-1)) */
+  double t_end;        /* T_{L-1} > 0; T_s = T_0 (T_end/T_0)^(s/(L-1)), L = schedule length */
   uint64_t seed;
   int32_t init;        /* HOBO_INIT_RANDOM or HOBO_INIT_GIVEN */
-  int32_t proposal;    /* HOBO_PROPOSAL_METROPOLIS, or MASKED with attempt masks */
-  const uint8_t* attempt; /* MASKED: device uint8 [ceil(B/16)][S][N] per instance,
+  int32_t proposal;    /* METROPOLIS, MASKED (attempt masks) or LEARNED (network) */
+  const uint8_t* attempt; /* MASKED: device uint8 [ceil(B/16)][sweeps][N] per instance,
                              concatenated; 1 = the 16-replica group visits the bit */
-  int32_t waves_per_block; /* waves sharing 16 replicas (1, 2, 4, 8; they split the
-                              columns); 0 = default.  Results do not depend on it. */
-  int32_t reserved;
+  int32_t waves_per_block; /* waves sharing 16 replicas (1, 2, 4, 8); 0 = default.
+                              Results do not depend on it. */
+  int32_t algorithm;   /* HOBO_ANNEAL_AUTO | SLABS | BLOCKS */
+  int32_t first_sweep; /* this call runs sweeps first_sweep .. first_sweep+sweeps-1 */
+  int32_t schedule_sweeps; /* L, length of the whole schedule; 0 = sweeps (first_sweep
+                              must then be 0) */
+  int32_t continue_best; /* 1: the best states start from best_x_out (their energies
+                            are recomputed) instead of the start states */
+  int32_t refresh;     /* LEARNED: sweeps per proposal segment, >= 1 */
+  const float* mlp;    /* LEARNED: device FP32 parameter vector (hobo_mlp_forward) */
+  float tau;           /* LEARNED: a tile attempts bit i iff some replica has p_i >= tau */
+  float p_floor;       /* LEARNED: ... or a floor draw u < p_floor (p_floor = 1: plain) */
 } hobo_anneal_params;
 
 /* Batched single-flip Metropolis simulated annealing (Sec. II.D.1) over one
  * or several instances.  Replica b of instance j:
  *   - initial state: x_inout (GIVEN) or bit i = top bit of Philox4x64-10 word
  *     i%4 at counter (b, 0, i/4, 1), key (seed, j) (RANDOM);
- *   - sweep s visits variables 0..N-1 in order (skipping bits whose attempt
- *     mask is 0 in MASKED mode); at variable i it draws
- *     u = (r >> 11) 2^-53 from word i%4 of Philox4x64-10 at counter
- *     (b, s, i/4, 0), key (seed, j), computes dE_i in the tensor precision,
- *     and accepts iff dE_i <= 0 or u < exp(-dE_i * beta_s) in double, with
- *     beta_s = 1 / T_s; on acceptance x_i flips and E += dE_i (double);
- *   - the best state is the initial one, then after each sweep the current
- *     one if its tracked energy is strictly lower.
+ *   - sweep s visits variables 0..N-1 in order (skipping the bits a replica's
+ *     16-replica group does not attempt in MASKED / LEARNED mode); at
+ *     variable i it draws u = (r >> 11) 2^-53 from word i%4 of Philox4x64-10
+ *     at counter (b, s, i/4, 0), key (seed, j), computes dE_i in the tensor
+ *     precision, and accepts iff dE_i <= 0 or dE_i * beta_s < -ln(u) in
+ *     double (the test u < exp(-dE_i beta_s)), with beta_s = 1 / T_s; on
+ *     acceptance x_i flips and E += dE_i (double);
+ *   - the best state is the initial one (or best_x_out with continue_best),
+ *     then after each sweep the current one if its tracked energy is lower.
+ * LEARNED: every `refresh` sweeps the library computes each replica's flip
+ * changes at its current state, evaluates the network on the features
+ * [x_i, beta_s dE_i, beta_s ||H_i||] (hobo_proposal_features) and lets a
+ * group attempt bit i during the segment iff some replica's logit is at least
+ * logit(tau) or u < p_floor, with u from Philox4x64-10 word i%4 at counter
+ * (group, s, i/4, 2), key (seed, j); attempted bits get the exact Metropolis
+ * test above.
  *  tensors     : host array of n_instances handles
  *  replicas    : host int64[n_instances], B_j >= 1
  *  x_inout     : device uint64, instance j's [W_j][B_j] block after those of
@@ -197,7 +217,7 @@ typedef struct {
  *  best_e_out  : device, one value per replica (instances concatenated):
  *                exact int64 energies of the best states when every instance
  *                is integer, else double energies recomputed in FP64
- *  trace_out   : optional device double [n_instances][S]: minimum over the
+ *  trace_out   : optional device double [n_instances][sweeps]: minimum over the
  *                instance's replicas of the tracked best energy after each sweep
  *  launch_mode : PER_INSTANCE (one launch sequence per instance),
  *                PERSISTENT (one persistent launch over all instances), or
@@ -207,6 +227,56 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances,
                               const int64_t* replicas, const hobo_anneal_params* params,
                               uint64_t* x_inout, uint64_t* best_x_out, void* best_e_out,
                               double* trace_out, int32_t launch_mode, void* stream);
+
+/* ------------------------------------------------------------- learned proposal */
+/* The flip-proposal network: a two-layer perceptron 3 -> 256 -> 1 mapping a
+ * bit's features [x_i, beta dE_i, beta ||H_i||] to a flip logit,
+ *   h = relu(W1^T f + b1),   logit = W2 . h + b2.
+ * The paper's search (Sec. II.D.1) has no learned part; this is the
+ * engine's addition, judged by the exact energy.  Parameters are one FP32
+ * vector of HOBO_MLP_PARAMS values: W1[f][u] at f*256+u, b1 at 768, W2 at
+ * 1024, b2 at 1280.  The forward pass uses W1 and W2 rounded to BF16 (nearest
+ * even) and FP32 biases, activations and sums. */
+#define HOBO_MLP_PARAMS 1281
+#define HOBO_MLP_ROW 1284
+#define HOBO_MLP_STATE (3 * HOBO_MLP_ROW) /* params | Adam m | Adam v, rows of 1284 */
+
+/* logits_out[m] for feats [M][3] (device FP32; params device FP32). */
+hobo_status hobo_mlp_forward(const float* params, const float* feats, int64_t M, float* logits_out, void* stream);
+
+/* Gradient of the mean binary cross-entropy over all M samples (one
+ * minibatch; 1 <= M <= 2^24) with respect to the parameters, evaluated through
+ * the BF16-rounded weights: grad_out device FP32 [HOBO_MLP_PARAMS], loss_out
+ * optional device FP32 scalar.  The same kernels and summation order as one
+ * step of hobo_mlp_train. */
+hobo_status hobo_mlp_grad(const float* params, const float* feats, const float* labels, int64_t M, float* grad_out,
+                          float* loss_out, void* stream);
+
+typedef struct {
+  int32_t batch;   /* samples per minibatch (the last one of an epoch may be shorter) */
+  int32_t epochs;
+  float lr, beta1, beta2, eps; /* Adam */
+  int64_t step0;   /* Adam steps already taken on this state (bias correction) */
+} hobo_mlp_train_params;
+
+/* Minibatch training on feats [M][3] and labels [M] (device FP32, labels 0/1)
+ * in sample order, one Adam step per minibatch: mean binary cross-entropy
+ * softplus(l) - y l, its gradient through the BF16-rounded weights applied
+ * to the FP32 master weights (Kingma & Ba bias-corrected Adam), gradient
+ * sums in a fixed order (deterministic).  state: device FP32
+ * [HOBO_MLP_STATE] = params | m | v, updated in place.  loss_trace: optional
+ * device FP32 [epochs * ceil(M / batch)], the minibatch loss before each step. */
+hobo_status hobo_mlp_train(float* state, const float* feats, const float* labels, int64_t M,
+                           const hobo_mlp_train_params* tp, float* loss_trace, void* stream);
+
+/* Features of every bit of B states: feats_out [B][N][3] FP32 =
+ * (x_i, beta dE_i, beta ||H_i||) with dE from hobo_local_fields (de: device
+ * [B][N], int64 for integer tensors, else FP32) and ||H_i|| the Euclidean norm
+ * of the coefficients of all monomials containing i.  With x_after (device
+ * [W][B]) and labels_out (device FP32 [B][N]) also the transition labels
+ * [x_i != x_after_i]. */
+hobo_status hobo_proposal_features(const hobo_tensor* t, const uint64_t* x_bits, const uint64_t* x_after, int64_t B,
+                                   const void* de, double beta, float* feats_out, float* labels_out, void* stream);
 
 /* ------------------------------------------------------------- timing */
 /* Kernel timing for measurement tools.  While enabled, each launch of the

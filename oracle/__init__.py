@@ -68,7 +68,7 @@ def _load():
         lib.orc_brute_force.restype = i32
         lib.orc_philox4x64.argtypes = [P, P, P]
         lib.orc_philox4x64.restype = None
-        lib.orc_anneal.argtypes = [i32, i32, P, P, P, i32, i64, i32, P, u64, u64, i32, P, P, P, P, P, P, P]
+        lib.orc_anneal.argtypes = [i32, i32, P, P, P, i32, i64, i32, P, u64, u64, i32, P, P, P, P, P, P, P, i32]
         lib.orc_anneal.restype = i32
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = i32
@@ -368,16 +368,23 @@ def schedule(t_start: float, t_end: float, sweeps: int) -> np.ndarray:
 
 
 def anneal(canon: Canonical, n_rep: int, sweeps: int, t_start: float, t_end: float, seed: int,
-           inst: int = 0, init_bits: np.ndarray | None = None, attempt: np.ndarray | None = None):
+           inst: int = 0, init_bits: np.ndarray | None = None, attempt: np.ndarray | None = None,
+           first_sweep: int = 0, schedule_sweeps: int = 0):
     """Batched Metropolis annealing; see orc_anneal in oracle.c for the rules.
 
+    Runs sweeps first_sweep .. first_sweep+sweeps-1 of a geometric schedule of
+    schedule_sweeps sweeps (default: the whole schedule, first_sweep 0); the
+    sweep index is the one of the schedule (temperature and random draws).
     Returns dict(final_bits [W][B], best_bits [W][B], best_e (exact, int64 or
-    float64), trace [S], accepts)."""
+    float64), trace [S], accepts); the best state starts at the start state."""
     n = canon.n_vars
     w = (n + 63) // 64
     ptr, idx = canon.csr()
     co, s = canon.fixed()
-    temps = schedule(t_start, t_end, sweeps)
+    total = schedule_sweeps if schedule_sweeps else sweeps
+    if first_sweep + sweeps > total:
+        raise ValueError("anneal: sweeps run past the schedule")
+    temps = np.ascontiguousarray(schedule(t_start, t_end, total)[first_sweep:first_sweep + sweeps])
     bits = np.zeros((w, n_rep), dtype=np.uint64) if init_bits is None else np.array(init_bits, dtype=np.uint64)
     best_bits = np.zeros((w, n_rep), dtype=np.uint64)
     bh = np.zeros(n_rep, dtype=np.int64)
@@ -387,7 +394,7 @@ def anneal(canon: Canonical, n_rep: int, sweeps: int, t_start: float, t_end: flo
     att = None if attempt is None else np.ascontiguousarray(attempt, dtype=np.uint8)
     rc = _load().orc_anneal(n, len(co), _p(ptr), _p(idx), _p(co), s, n_rep, sweeps, _p(temps), seed, inst,
                             1 if init_bits is not None else 0, _p(bits), _p(best_bits), _p(bh), _p(bl),
-                            _p(trace), None if att is None else _p(att), _p(nacc))
+                            _p(trace), None if att is None else _p(att), _p(nacc), int(first_sweep))
     if rc != 0:
         raise ValueError("anneal: bad arguments")
     vals = [(int(h) << 64) | int(l) for h, l in zip(bh, bl)]

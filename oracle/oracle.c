@@ -245,7 +245,7 @@ int orc_anneal(int n_vars, int n_mono, const int64_t* mono_ptr, const int32_t* m
                const int64_t* coeff, int s_scale, int64_t B, int S, const double* temps,
                uint64_t seed, uint64_t inst, int init_given, uint64_t* bits_inout,
                uint64_t* best_bits_out, int64_t* best_hi, uint64_t* best_lo, double* trace_out,
-               const unsigned char* attempt, int64_t* n_accept_out) {
+               const unsigned char* attempt, int64_t* n_accept_out, int s0) {
   if (n_vars > 4096) return -1;
   int64_t* cnt = (int64_t*)calloc((size_t)n_vars + 1, sizeof(int64_t));
   for (int m = 0; m < n_mono; ++m)
@@ -286,7 +286,7 @@ int orc_anneal(int n_vars, int n_mono, const int64_t* mono_ptr, const int32_t* m
         }
         i128 de = x[i] ? -g : g;
         double ded = fixed_to_double(de, s_scale);
-        double u = u01(draw(seed, inst, (uint64_t)b, (uint64_t)s, i, 0));
+        double u = u01(draw(seed, inst, (uint64_t)b, (uint64_t)(s0 + s), i, 0));
         if (ded <= 0.0 || u < exp(-ded * beta)) {
           x[i] ^= 1;
           e += de;

@@ -22,7 +22,7 @@ ARCH = "gfx950"
 NO_PK_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["anneal_kernels.hip", "eval_kernels.hip", "timing.hip", "pack.cpp", "canon.cpp", "abi.cpp"]
+SOURCES = ["anneal_kernels.hip", "anneal_block.hip", "mlp_kernels.hip", "eval_kernels.hip", "timing.hip", "pack.cpp", "canon.cpp", "abi.cpp"]
 
 
 def _compile(src: str) -> str:

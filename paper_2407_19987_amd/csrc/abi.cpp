@@ -87,11 +87,57 @@ struct AnnealEntry {
   int32_t mode = 0;
   void* work = nullptr;
   hobo::AnnealTables tb;
-  std::vector<int> item_first;
-  std::vector<int> ct_of, nw_of;
-  int ct = 1, nw = 1;
+  std::vector<hobo::AnnealPlan> plans;  // PERSISTENT / GRAPH: one plan; PER_INSTANCE: one per instance
   hipGraphExec_t exec = nullptr;
+  // LEARNED proposal: per-instance fields layout, row norms and workspaces
+  struct Learn {
+    hobo::Packed* fields = nullptr;
+    const hobo::Tensor* t = nullptr;
+    const double* rnorm = nullptr;
+    void* de = nullptr;
+    unsigned char* mask = nullptr;
+    const uint64_t* x = nullptr;
+    int64_t B = 0;
+    int rt = 1, ct = 1;
+  };
+  std::vector<Learn> learn;
+  std::vector<double> beta;  // inverse temperatures of the call's sweeps
+  int refresh = 0;
+  const float* mlp = nullptr;
+  float lthr = 0.0f;
+  double p_floor = 0.0;
+  int precision = 0;
 };
+
+// The whole sequence of one plan; with the LEARNED proposal every `refresh`
+// sweeps the fields of the current states feed the network and the next
+// segment's attempt masks.
+int enqueue_plan(const AnnealEntry& e, const hobo::AnnealPlan& pl, void* stream, std::string* err) {
+  if (e.refresh == 0) return hobo::enqueue_anneal_seq(e.tb, pl, stream, err);
+  if (int s = hobo::enqueue_anneal_setup(e.tb, pl, stream, err)) return s;
+  const int s_end = pl.s_first + pl.sweeps;
+  if (pl.sweeps == 0) {
+    if (int s = hobo::enqueue_anneal_sweeps(e.tb, pl, pl.s_first, pl.s_first, pl.s_first, 0, pl.cont, stream, err))
+      return s;
+  }
+  for (int s0 = pl.s_first; s0 < s_end; s0 += e.refresh) {
+    const int len = std::min(e.refresh, s_end - s0);
+    const double beta0 = e.beta[(size_t)(s0 - pl.s_first)];
+    for (int j = pl.inst0; j < pl.inst0 + pl.ninst; ++j) {
+      const AnnealEntry::Learn& L = e.learn[(size_t)j];
+      hobo::EvalArgs a{L.fields, L.t, L.x, L.B, L.de, nullptr, nullptr, L.rt, L.ct, stream};
+      if (int s = hobo::launch_eval(a, err)) return s;
+      if (int s = hobo::proposal_masks(e.mlp, reinterpret_cast<const unsigned long long*>(L.x), L.B, L.t->n_vars,
+                                       L.de, L.t->integer ? 1 : 0, beta0, L.rnorm, e.lthr, e.p_floor, pl.seed,
+                                       (unsigned long long)j, s0, len, L.mask, (hipStream_t)stream, err))
+        return s;
+    }
+    if (int s = hobo::enqueue_anneal_sweeps(e.tb, pl, s0, s0 + len, s0, len, pl.cont || s0 > pl.s_first, stream,
+                                            err))
+      return s;
+  }
+  return hobo::enqueue_anneal_finish(e.tb, pl, stream, err);
+}
 std::mutex g_anneal_mu;
 std::list<AnnealEntry> g_anneal;  // most recent first
 
@@ -293,8 +339,11 @@ hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_
       if (int s = hobo::get_packed(&t->t, hobo::M_ENERGY, p, &pk, &err)) return fail(s, err);
     if (fn_mask & 2u)
       if (int s = hobo::get_packed(&t->t, hobo::M_FIELDS, p, &pk, &err)) return fail(s, err);
-    if (fn_mask & 4u)
+    if (fn_mask & 4u) {
       if (int s = hobo::get_packed(&t->t, hobo::M_SLABS, p, &pk, &err)) return fail(s, err);
+      if (t->t.order <= 3 && p != HOBO_PREC_INT8X4)
+        if (int s = hobo::get_packed(&t->t, hobo::M_BLOCKS, p, &pk, &err)) return fail(s, err);
+    }
   }
   if (fn_mask & 4u) {
     hobo::TermsDev* td;
@@ -387,13 +436,26 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   if (n_instances < 1) return fail(HOBO_ERR_INVALID_ARG, "n_instances must be >= 1");
   const hobo_anneal_params& P = *params;
   if (P.sweeps < 0) return fail(HOBO_ERR_INVALID_ARG, "sweeps must be >= 0");
+  const int64_t L = P.schedule_sweeps == 0 ? (int64_t)P.sweeps : (int64_t)P.schedule_sweeps;
+  if (P.schedule_sweeps < 0 || P.first_sweep < 0) return fail(HOBO_ERR_INVALID_ARG, "negative sweep index");
+  if (P.schedule_sweeps == 0 && P.first_sweep != 0)
+    return fail(HOBO_ERR_INVALID_ARG, "first_sweep needs schedule_sweeps");
+  if ((int64_t)P.first_sweep + P.sweeps > L) return fail(HOBO_ERR_INVALID_ARG, "sweeps run past the schedule");
   if (!(P.t_start > 0.0) || !(P.t_end > 0.0) || !std::isfinite(P.t_start) || !std::isfinite(P.t_end))
     return fail(HOBO_ERR_INVALID_ARG, "temperatures must be finite and > 0");
   if (P.init != HOBO_INIT_RANDOM && P.init != HOBO_INIT_GIVEN) return fail(HOBO_ERR_INVALID_ARG, "unknown init");
-  if (P.proposal != HOBO_PROPOSAL_METROPOLIS && P.proposal != HOBO_PROPOSAL_MASKED)
+  if (P.continue_best != 0 && P.continue_best != 1) return fail(HOBO_ERR_INVALID_ARG, "continue_best must be 0 or 1");
+  if (P.proposal != HOBO_PROPOSAL_METROPOLIS && P.proposal != HOBO_PROPOSAL_MASKED &&
+      P.proposal != HOBO_PROPOSAL_LEARNED)
     return fail(HOBO_ERR_INVALID_ARG, "unknown proposal");
   if (P.proposal == HOBO_PROPOSAL_MASKED && !P.attempt)
     return fail(HOBO_ERR_INVALID_ARG, "MASKED proposal needs attempt masks");
+  if (P.proposal == HOBO_PROPOSAL_LEARNED) {
+    if (!P.mlp) return fail(HOBO_ERR_INVALID_ARG, "LEARNED proposal needs network weights");
+    if (P.refresh < 1) return fail(HOBO_ERR_INVALID_ARG, "refresh must be >= 1");
+    if (!(P.p_floor >= 0.0f && P.p_floor <= 1.0f)) return fail(HOBO_ERR_INVALID_ARG, "p_floor must be in [0, 1]");
+    if (std::isnan(P.tau)) return fail(HOBO_ERR_INVALID_ARG, "tau is NaN");
+  }
   if (P.precision < HOBO_PREC_FP32 || P.precision > HOBO_PREC_INT8X4)
     return fail(HOBO_ERR_PRECISION, "annealing precision must be FP32, BF16X2, BF16X3 or INT8X4");
   if (launch_mode < HOBO_LAUNCH_PER_INSTANCE || launch_mode > HOBO_LAUNCH_GRAPH)
@@ -401,6 +463,8 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   if (P.waves_per_block != 0 && P.waves_per_block != 1 && P.waves_per_block != 2 && P.waves_per_block != 4 &&
       P.waves_per_block != 8)
     return fail(HOBO_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
+  if (P.algorithm < HOBO_ANNEAL_AUTO || P.algorithm > HOBO_ANNEAL_BLOCKS)
+    return fail(HOBO_ERR_INVALID_ARG, "unknown algorithm");
   bool all_int = true, any_int = false;
   int max_n = 0;
   for (int j = 0; j < n_instances; ++j) {
@@ -414,6 +478,14 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   if (P.precision == HOBO_PREC_INT8X4 && !all_int) return fail(HOBO_ERR_PRECISION, "INT8X4 needs integer tensors");
   if (P.precision == HOBO_PREC_INT8X4 && max_n > 64)
     return fail(HOBO_ERR_UNSUPPORTED, "INT8X4 annealing supports at most 64 variables");
+  // kernel of each instance: blocked where it applies (and is not overridden)
+  std::vector<int> blocked((size_t)n_instances);
+  for (int j = 0; j < n_instances; ++j) {
+    const bool can = tensors[j]->t.order <= 3 && P.precision != HOBO_PREC_INT8X4;
+    if (P.algorithm == HOBO_ANNEAL_BLOCKS && !can)
+      return fail(HOBO_ERR_UNSUPPORTED, "the blocked annealer covers orders up to 3 in FP32 / BF16 precisions");
+    blocked[(size_t)j] = P.algorithm == HOBO_ANNEAL_SLABS ? 0 : (can ? 1 : 0);
+  }
   if (hobo_status s = need_device()) return s;
   hipStream_t st = (hipStream_t)stream;
   std::string err;
@@ -422,7 +494,8 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   std::vector<hobo::Packed*> pks((size_t)n_instances);
   std::vector<hobo::TermsDev*> tds((size_t)n_instances);
   for (int j = 0; j < n_instances; ++j) {
-    if (int s = hobo::get_packed(&tensors[j]->t, hobo::M_SLABS, P.precision, &pks[(size_t)j], &err)) return fail(s, err);
+    const int mode = blocked[(size_t)j] ? hobo::M_BLOCKS : hobo::M_SLABS;
+    if (int s = hobo::get_packed(&tensors[j]->t, mode, P.precision, &pks[(size_t)j], &err)) return fail(s, err);
     if (int s = hobo::get_terms(&tensors[j]->t, &tds[(size_t)j], &err)) return fail(s, err);
   }
   const int S = P.sweeps;
@@ -451,19 +524,49 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     max_groups = std::max(max_groups, (tds[(size_t)j]->n_mono + 4095) / 4096);
   }
   size_t off_ones = align(off_term + term_bytes);
-  size_t total = align(off_ones + 256);
+  const bool learned = P.proposal == HOBO_PROPOSAL_LEARNED;
+  size_t off_learn = align(off_ones + 256);
+  size_t learn_bytes = 0;
+  if (learned)
+    for (int j = 0; j < n_instances; ++j) {
+      const int64_t n = tensors[j]->t.n_vars;
+      learn_bytes += align((size_t)replicas[j] * n * (tensors[j]->t.integer ? 8 : 4));
+      learn_bytes += align((size_t)((replicas[j] + 15) / 16) * P.refresh * n);
+    }
+  size_t total = align(off_learn + learn_bytes);
+  std::vector<hobo::Packed*> fpks((size_t)n_instances, nullptr);
+  std::vector<const double*> rns((size_t)n_instances, nullptr);
+  if (learned)
+    for (int j = 0; j < n_instances; ++j) {
+      if (int s = hobo::get_packed(&tensors[j]->t, hobo::M_FIELDS, P.precision, &fpks[(size_t)j], &err))
+        return fail(s, err);
+      if (int s = hobo::get_row_norms(&tensors[j]->t, &rns[(size_t)j], &err)) return fail(s, err);
+    }
 
-  // host tables
+  // inverse temperatures of this call's sweeps
   std::vector<double> beta((size_t)std::max(S, 1));
   for (int s = 0; s < S; ++s) {
-    double T = S == 1 ? P.t_start : P.t_start * std::pow(P.t_end / P.t_start, (double)s / (double)(S - 1));
+    const int64_t sg = (int64_t)P.first_sweep + s;
+    double T = L == 1 ? P.t_start : P.t_start * std::pow(P.t_end / P.t_start, (double)sg / (double)(L - 1));
     beta[(size_t)s] = 1.0 / T;
   }
-  // launch shape
-  int ct = 1, nw = 1;  // column tiles per wave, waves per work-group
-  int maxT = 1;
-  for (int j = 0; j < n_instances; ++j) maxT = std::max(maxT, (tensors[j]->t.n_vars + 15) / 16);
-  hobo::anneal_shape(maxT, P.waves_per_block, &ct, &nw);
+  const int init_random = P.init == HOBO_INIT_RANDOM ? 1 : 0;
+  auto base_plan = [&]() {
+    hobo::AnnealPlan pl;
+    pl.sweeps = S;
+    pl.s_first = P.first_sweep;
+    pl.seed = P.seed;
+    pl.init_random = init_random;
+    pl.cont = P.continue_best;
+    pl.masked = P.proposal != HOBO_PROPOSAL_METROPOLIS ? 1 : 0;
+    pl.prec = P.precision;
+    return pl;
+  };
+  // blocked kernel width: one 16-replica group per CU wants every wave; many groups fewer waves
+  auto blk_waves = [&](int64_t tiles) {
+    if (P.waves_per_block) return (int)P.waves_per_block;
+    return tiles <= 512 ? 4 : (tiles <= 2048 ? 2 : 1);
+  };
 
   // cache lookup
   std::vector<uint64_t> key;
@@ -474,20 +577,32 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     key.push_back((uint64_t)replicas[j]);
   }
   {
-    uint64_t pbits[5];
+    uint64_t pbits[7];
     std::memcpy(&pbits[0], &P.t_start, 8);
     std::memcpy(&pbits[1], &P.t_end, 8);
     pbits[2] = P.seed;
     pbits[3] = ((uint64_t)(uint32_t)P.sweeps << 32) | (uint32_t)P.precision;
-    pbits[4] = ((uint64_t)(uint32_t)P.init << 32) | ((uint32_t)P.proposal << 8) | (uint32_t)nw;
+    pbits[4] = ((uint64_t)(uint32_t)P.init << 32) | ((uint32_t)P.proposal << 8) | (uint32_t)P.waves_per_block;
+    pbits[5] = ((uint64_t)(uint32_t)P.first_sweep << 32) | (uint32_t)L;
+    pbits[6] = ((uint64_t)(uint32_t)P.continue_best << 32) | (uint32_t)P.algorithm;
     for (auto v : pbits) key.push_back(v);
   }
   key.push_back((uint64_t)(uintptr_t)P.attempt);
+  if (learned) {
+    uint64_t lb[2];
+    uint32_t tb32, pf32;
+    std::memcpy(&tb32, &P.tau, 4);
+    std::memcpy(&pf32, &P.p_floor, 4);
+    lb[0] = ((uint64_t)tb32 << 32) | pf32;
+    lb[1] = (uint64_t)(uint32_t)P.refresh;
+    key.push_back(lb[0]);
+    key.push_back(lb[1]);
+    key.push_back((uint64_t)(uintptr_t)P.mlp);
+  }
   key.push_back((uint64_t)(uintptr_t)x_inout);
   key.push_back((uint64_t)(uintptr_t)best_x_out);
   key.push_back((uint64_t)(uintptr_t)best_e_out);
   key.push_back((uint64_t)(uintptr_t)trace_out);
-  const int init_random = P.init == HOBO_INIT_RANDOM ? 1 : 0;
 
   std::lock_guard<std::mutex> lock(g_anneal_mu);
   AnnealEntry* ent = nullptr;
@@ -505,10 +620,19 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     char* wb = static_cast<char*>(ne.work);
     std::vector<hobo::AnnealInstDev> inst((size_t)n_instances);
     std::vector<hobo::InstSmall> small((size_t)n_instances);
-    std::vector<hobo::AnnealItem> items;
-    ne.item_first.assign((size_t)n_instances + 1, 0);
+    std::vector<std::vector<hobo::AnnealItem>> items_of((size_t)n_instances);
     int64_t xoff = 0, roff = 0, toff = 0, att_off = 0;
-    size_t term_off = 0;
+    size_t term_off = 0, learn_off = 0;
+    int max_ct = 1, max_nw = 1;
+    ne.beta = beta;
+    if (learned) {
+      ne.refresh = P.refresh;
+      ne.mlp = P.mlp;
+      ne.p_floor = (double)P.p_floor;
+      ne.precision = P.precision;
+      const double tau = (double)P.tau;
+      ne.lthr = tau <= 0.0 ? -INFINITY : (tau >= 1.0 ? INFINITY : (float)std::log(tau / (1.0 - tau)));
+    }
     for (int j = 0; j < n_instances; ++j) {
       const hobo::Tensor& T = tensors[j]->t;
       const hobo::Packed* pk = pks[(size_t)j];
@@ -520,17 +644,37 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       d.chunks = pk->d_chunks;
       d.runs = reinterpret_cast<const unsigned long long*>(pk->d_runs);
       d.slabs = pk->d_slabs;
+      d.blocks = pk->d_blocks;
+      d.triples = pk->d_triples;
+      d.nblocks = pk->nblocks;
       d.x = reinterpret_cast<unsigned long long*>(x_inout + xoff);
       d.best_x = reinterpret_cast<unsigned long long*>(best_x_out + xoff);
       d.e_track = reinterpret_cast<double*>(wb + off_e) + roff;
       d.best_track = reinterpret_cast<double*>(wb + off_best) + roff;
       d.trace_part = S > 0 ? reinterpret_cast<double*>(wb + off_trace) + toff * S : nullptr;
       d.attempt = P.proposal == HOBO_PROPOSAL_MASKED ? P.attempt + att_off : nullptr;
+      if (learned) {
+        AnnealEntry::Learn L;
+        L.fields = fpks[(size_t)j];
+        L.t = &T;
+        L.rnorm = rns[(size_t)j];
+        L.de = wb + off_learn + learn_off;
+        learn_off += align((size_t)Bj * T.n_vars * (T.integer ? 8 : 4));
+        L.mask = reinterpret_cast<unsigned char*>(wb + off_learn + learn_off);
+        learn_off += align((size_t)nt * P.refresh * T.n_vars);
+        L.x = x_inout + xoff;
+        L.B = Bj;
+        eval_shape(T, P.precision, Bj, &L.rt, &L.ct);
+        d.attempt = L.mask;
+        ne.learn.push_back(L);
+      }
       d.B = Bj;
       d.n_vars = T.n_vars;
       d.W = W;
       d.integer = T.integer ? 1 : 0;
       d.inst_id = (unsigned long long)j;
+      d.n_chunks = pk->nchunks;
+      d.n_tiles = (unsigned)pk->ntiles;
       hobo::InstSmall& sm = small[(size_t)j];
       sm.rec = tds[(size_t)j]->d_rec;
       sm.n_mono = tds[(size_t)j]->n_mono;
@@ -542,6 +686,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       sm.x = d.x;
       sm.best_x = d.best_x;
       sm.e_track = d.e_track;
+      sm.best_track = d.best_track;
       sm.best_out = all_int ? (void*)(static_cast<int64_t*>(best_e_out) + roff)
                             : (void*)(static_cast<double*>(best_e_out) + roff);
       sm.trace_part = d.trace_part;
@@ -550,26 +695,62 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       sm.ntiles16 = nt;
       sm.term_part = wb + off_term + term_off;
       term_off += align(hobo::term_workspace_bytes(&T, Bj));
-      ne.item_first[(size_t)j] = (int)items.size();
-      for (int q = 0; q < nt; ++q) items.push_back(hobo::AnnealItem{j, q});
+      for (int q = 0; q < nt; ++q) items_of[(size_t)j].push_back(hobo::AnnealItem{j, q});
       xoff += (int64_t)W * Bj;
       roff += Bj;
       toff += nt;
       att_off += (int64_t)nt * S * T.n_vars;
-      int ctj, nwj;
-      hobo::anneal_shape((T.n_vars + 15) / 16, P.waves_per_block, &ctj, &nwj);
-      ne.ct_of.push_back(ctj);
-      ne.nw_of.push_back(nwj);
-      d.n_chunks = pk->nchunks;
-      d.n_tiles = (unsigned)pk->ntiles;
+      if (!blocked[(size_t)j]) {
+        int ctj, nwj;
+        hobo::anneal_shape((T.n_vars + 15) / 16, P.waves_per_block, &ctj, &nwj);
+        max_ct = std::max(max_ct, ctj);
+        max_nw = std::max(max_nw, nwj);
+      }
     }
-    ne.item_first[(size_t)n_instances] = (int)items.size();
-    if (launch_mode != HOBO_LAUNCH_PER_INSTANCE) {
-      // persistent order: most expensive instances first (cost ~ tiles per sweep)
-      std::stable_sort(items.begin(), items.end(), [&](const hobo::AnnealItem& a, const hobo::AnnealItem& b) {
-        return pks[(size_t)a.inst]->ntiles > pks[(size_t)b.inst]->ntiles;
-      });
+    // item list: blocked-kernel items first, then slab-kernel items; in the
+    // persistent modes each part runs most expensive instances first
+    std::vector<hobo::AnnealItem> items;
+    auto cost = [&](int j) { return (int64_t)pks[(size_t)j]->ntiles; };
+    if (launch_mode == HOBO_LAUNCH_PER_INSTANCE) {
+      for (int j = 0; j < n_instances; ++j) {
+        hobo::AnnealPlan pl = base_plan();
+        pl.item0 = (int)items.size();
+        pl.inst0 = j;
+        pl.ninst = 1;
+        const int nt = (int)items_of[(size_t)j].size();
+        if (blocked[(size_t)j]) {
+          pl.n_blk = nt;
+          pl.nw_blk = blk_waves(nt);
+        } else {
+          pl.n_slab = nt;
+          hobo::anneal_shape((tensors[j]->t.n_vars + 15) / 16, P.waves_per_block, &pl.ct, &pl.nw);
+        }
+        items.insert(items.end(), items_of[(size_t)j].begin(), items_of[(size_t)j].end());
+        ne.plans.push_back(pl);
+      }
+    } else {
+      std::vector<int> ord((size_t)n_instances);
+      for (int j = 0; j < n_instances; ++j) ord[(size_t)j] = j;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost(a) > cost(b); });
+      hobo::AnnealPlan pl = base_plan();
+      pl.inst0 = 0;
+      pl.ninst = n_instances;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int j : ord)
+          if (blocked[(size_t)j] == (pass == 0 ? 1 : 0)) {
+            items.insert(items.end(), items_of[(size_t)j].begin(), items_of[(size_t)j].end());
+            (pass == 0 ? pl.n_blk : pl.n_slab) += (int)items_of[(size_t)j].size();
+          }
+      pl.nw_blk = blk_waves(pl.n_blk);
+      // slab kernel shape: widest instance decides (all share one launch)
+      int maxT = 1;
+      for (int j = 0; j < n_instances; ++j)
+        if (!blocked[(size_t)j]) maxT = std::max(maxT, (tensors[j]->t.n_vars + 15) / 16);
+      hobo::anneal_shape(maxT, P.waves_per_block, &pl.ct, &pl.nw);
+      ne.plans.push_back(pl);
     }
+    (void)max_ct;
+    (void)max_nw;
     ne.tb.d_inst = reinterpret_cast<hobo::AnnealInstDev*>(wb + off_inst);
     ne.tb.d_items = reinterpret_cast<hobo::AnnealItem*>(wb + off_items);
     ne.tb.d_small = reinterpret_cast<hobo::InstSmall*>(wb + off_small);
@@ -579,8 +760,6 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     ne.tb.max_W = max_W;
     ne.tb.max_groups = max_groups;
     ne.tb.d_ones = reinterpret_cast<const unsigned char*>(wb + off_ones);
-    ne.ct = ct;
-    ne.nw = nw;
     hipError_t e = hipMemcpy(ne.tb.d_inst, inst.data(), inst.size() * sizeof(inst[0]), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(ne.tb.d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice);
@@ -605,8 +784,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       int s = HOBO_OK;
       e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        s = hobo::enqueue_anneal_seq(ne.tb, n_instances, S, P.seed, init_random, P.precision, ct, nw, 0,
-                                     ne.tb.n_items, 0, n_instances, (void*)cap, &err);
+        s = enqueue_plan(ne, ne.plans[0], (void*)cap, &err);
         hipError_t e2 = hipStreamEndCapture(cap, &graph);
         if (e == hipSuccess) e = e2;
       }
@@ -629,17 +807,89 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   int s = HOBO_OK;
   if (launch_mode == HOBO_LAUNCH_GRAPH) {
     return hip_status(hipGraphLaunch(ent->exec, st), "hipGraphLaunch");
-  } else if (launch_mode == HOBO_LAUNCH_PERSISTENT) {
-    s = hobo::enqueue_anneal_seq(ent->tb, n_instances, S, P.seed, init_random, P.precision, ent->ct, ent->nw, 0,
-                                 ent->tb.n_items, 0, n_instances, stream, &err);
-  } else {
-    for (int j = 0; j < n_instances && s == HOBO_OK; ++j) {
-      int i0 = ent->item_first[(size_t)j], ni = ent->item_first[(size_t)j + 1] - i0;
-      s = hobo::enqueue_anneal_seq(ent->tb, n_instances, S, P.seed, init_random, P.precision, ent->ct_of[(size_t)j],
-                                   ent->nw_of[(size_t)j], i0, ni, j, 1, stream, &err);
-    }
   }
+  for (size_t k = 0; k < ent->plans.size() && s == HOBO_OK; ++k) s = enqueue_plan(*ent, ent->plans[k], stream, &err);
   if (s) return fail(s, err);
+  return ok();
+}
+
+// ------------------------------------------------------------ learned proposal
+hobo_status hobo_mlp_forward(const float* params, const float* feats, int64_t M, float* logits_out, void* stream) {
+  g_err.clear();
+  if (!params || !feats || !logits_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (M < 0 || M > (int64_t)1 << 40) return fail(HOBO_ERR_INVALID_ARG, "M out of range");
+  if (hobo_status s = need_device()) return s;
+  std::string err;
+  if (int s = hobo::mlp_forward(params, feats, M, logits_out, (hipStream_t)stream, &err)) return fail(s, err);
+  return ok();
+}
+
+hobo_status hobo_mlp_train(float* state, const float* feats, const float* labels, int64_t M,
+                           const hobo_mlp_train_params* tp, float* loss_trace, void* stream) {
+  g_err.clear();
+  if (!state || !feats || !labels || !tp) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (M < 1 || M > (int64_t)1 << 40) return fail(HOBO_ERR_INVALID_ARG, "M out of range");
+  if (tp->batch < 1 || tp->batch > (1 << 24)) return fail(HOBO_ERR_INVALID_ARG, "batch out of range");
+  if (tp->epochs < 0) return fail(HOBO_ERR_INVALID_ARG, "epochs must be >= 0");
+  if (!(tp->lr > 0.0f) || !(tp->beta1 >= 0.0f && tp->beta1 < 1.0f) || !(tp->beta2 >= 0.0f && tp->beta2 < 1.0f) ||
+      !(tp->eps > 0.0f) || tp->step0 < 0)
+    return fail(HOBO_ERR_INVALID_ARG, "invalid optimiser parameters");
+  if (hobo_status s = need_device()) return s;
+  hipStream_t st = (hipStream_t)stream;
+  std::string err;
+  void* part = nullptr;
+  if (hobo_status s = hip_status(hipMallocAsync(&part, hobo::mlp_train_workspace(tp->batch), st), "hipMallocAsync"))
+    return s;
+  int64_t step = tp->step0, k = 0;
+  int rc = HOBO_OK;
+  for (int e = 0; e < tp->epochs && rc == HOBO_OK; ++e)
+    for (int64_t m0 = 0; m0 < M && rc == HOBO_OK; m0 += tp->batch, ++k) {
+      const int mb = (int)std::min<int64_t>(tp->batch, M - m0);
+      ++step;
+      const float bc1 = (float)(1.0 - std::pow((double)tp->beta1, (double)step));
+      const float bc2 = (float)(1.0 - std::pow((double)tp->beta2, (double)step));
+      rc = hobo::mlp_train_step(state, feats, labels, m0, mb, tp->lr, tp->beta1, tp->beta2, tp->eps, bc1, bc2,
+                                static_cast<float*>(part), loss_trace ? loss_trace + k : nullptr, st, &err);
+    }
+  (void)hipFreeAsync(part, st);
+  if (rc) return fail(rc, err);
+  return ok();
+}
+
+hobo_status hobo_mlp_grad(const float* params, const float* feats, const float* labels, int64_t M, float* grad_out,
+                          float* loss_out, void* stream) {
+  g_err.clear();
+  if (!params || !feats || !labels || !grad_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (M < 1 || M > (1 << 24)) return fail(HOBO_ERR_INVALID_ARG, "M must be in [1, 2^24]");
+  if (hobo_status s = need_device()) return s;
+  hipStream_t st = (hipStream_t)stream;
+  std::string err;
+  void* part = nullptr;
+  if (hobo_status s = hip_status(hipMallocAsync(&part, hobo::mlp_train_workspace((int)M), st), "hipMallocAsync"))
+    return s;
+  int rc = hobo::mlp_grad(params, feats, labels, (int)M, static_cast<float*>(part), grad_out, loss_out, st, &err);
+  (void)hipFreeAsync(part, st);
+  if (rc) return fail(rc, err);
+  return ok();
+}
+
+hobo_status hobo_proposal_features(const hobo_tensor* tc, const uint64_t* x_bits, const uint64_t* x_after, int64_t B,
+                                   const void* de, double beta, float* feats_out, float* labels_out, void* stream) {
+  g_err.clear();
+  if (!tc || !x_bits || !de || !feats_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (labels_out && !x_after) return fail(HOBO_ERR_INVALID_ARG, "labels need x_after");
+  if (B < 1 || B > (int64_t)1 << 40) return fail(HOBO_ERR_INVALID_ARG, "B out of range");
+  if (!std::isfinite(beta)) return fail(HOBO_ERR_INVALID_ARG, "beta must be finite");
+  if (hobo_status s = need_device()) return s;
+  hobo_tensor* t = const_cast<hobo_tensor*>(tc);
+  std::string err;
+  const double* rn = nullptr;
+  if (int s = hobo::get_row_norms(&t->t, &rn, &err)) return fail(s, err);
+  if (int s = hobo::proposal_features(reinterpret_cast<const unsigned long long*>(x_bits),
+                                      reinterpret_cast<const unsigned long long*>(x_after), B, t->t.n_vars, de,
+                                      t->t.integer ? 1 : 0, beta, rn, feats_out, labels_out, (hipStream_t)stream,
+                                      &err))
+    return fail(s, err);
   return ok();
 }
 

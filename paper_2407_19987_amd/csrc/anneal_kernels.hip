@@ -11,17 +11,7 @@
 
 namespace hobo {
 
-// ============================================================ annealer
-struct AnnealParams {
-  const AnnealInstDev* insts;
-  const AnnealItem* items;
-  int n_items;
-  int sweeps;
-  const double* beta;
-  unsigned long long seed;
-  const unsigned char* ones;  // a device byte equal to 1 (attempt flag without masks)
-};
-
+// ============================================================ annealer (per-bit slabs)
 // k-th 16-column tile of wave w among cs waves, folded (w, 2cs-1-w, 2cs+w, ...)
 // so that the triangular layouts give every wave the same amount of work
 __host__ __device__ inline int wave_tile(int k, int w, int cs) { return k * cs + ((k & 1) ? cs - 1 - w : w); }
@@ -98,15 +88,20 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
         smeta[slot][q] = __builtin_bit_cast(ChunkMeta, gld(reinterpret_cast<const unsigned long long*>(I.chunks) + c0 + q));
     };
     load_bits(sbits[w], I.x, I.W, I.B, r0, 16, lane);
-    if (w == 0) load_bits(sbest, I.x, I.W, I.B, r0, 16, lane);
+    if (w == 0) load_bits(sbest, p.cont ? I.best_x : I.x, I.W, I.B, r0, 16, lane);
     for (int q = threadIdx.x; q < N; q += blockDim.x) sa[q] = gld(&I.slabs[q].a_f);
-    if (C > 0) stage_meta(0, 0);
-    if (nblk > 1) stage_meta(1, 1);
+    {  // the first two blocks of the stream, in the buffers their position selects
+      const int par = nblk > 2 ? (int)(((long long)p.s_begin * nblk) & 1) : 0;
+      if (C > 0) stage_meta(0, par);
+      if (nblk > 1) stage_meta(1, par ^ 1);
+    }
     const long long myrow = r0 + orow;
     const bool live_row = owner && myrow < I.B;
-    double E = 0.0;
-    if (live_row) E = gld(I.e_track + myrow);
-    double bestE = E;
+    double E = 0.0, bestE = 0.0;
+    if (live_row) {
+      E = gld(I.e_track + myrow);
+      bestE = p.cont ? gld(I.best_track + myrow) : E;
+    }
     unsigned long long rw[4] = {0, 0, 0, 0};
     int rw_key = -1;  // (sweep, 16-bit block) of the Philox words held
     __syncthreads();
@@ -114,7 +109,8 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
     AccT<P> acc[CTW];
 #pragma unroll
     for (int k = 0; k < CTW; ++k) acc_zero<P>(acc[k]);
-    const unsigned char* att_base = I.attempt ? I.attempt + (size_t)item.tile16 * S * N : p.ones;
+    const unsigned char* att_base =
+        I.attempt ? I.attempt + ((size_t)item.tile16 * p.mask_rows - p.mask_s0) * N : p.ones;
     const int att_on = I.attempt ? 1 : 0;
     // with at most two blocks both stay staged (buffer = block); with more,
     // blocks are restaged in stream order and alternate buffers
@@ -154,7 +150,7 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
       }
     };
 
-    int cs_cur = 0;  // sweep the consumer is in
+    int cs_cur = p.s_begin;  // sweep the consumer is in
     auto end_sweep = [&](int s) {
       if (live_row && E < bestE) {
         bestE = E;
@@ -271,14 +267,14 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
       }
     };
     // the run in epochs of kTraceEpoch sweeps; the trace leaves LDS between them
-    for (int s0 = 0; s0 < S || (S == 0 && s0 == 0); s0 += kTraceEpoch) {
-      const int s1 = S - s0 < kTraceEpoch ? S : s0 + kTraceEpoch;
+    for (int s0 = p.s_begin; s0 < p.s_end; s0 += kTraceEpoch) {
+      const int s1 = p.s_end - s0 < kTraceEpoch ? p.s_end : s0 + kTraceEpoch;
       ps = s0;
       pc = 0;
       ps_end = C > 0 ? s1 : s0;
       // inverse temperatures of this epoch (the stream reads them from LDS)
       __syncthreads();
-      for (int q = threadIdx.x; q < s1 - s0; q += blockDim.x) sbeta[q] = gld(p.beta + s0 + q);
+      for (int q = threadIdx.x; q < s1 - s0; q += blockDim.x) sbeta[(s0 + q) % kTraceEpoch] = gld(p.beta + (s0 - p.s_first) + q);
       __syncthreads();
       if (nblk > 2)
         run(std::integral_constant<bool, true>{});
@@ -286,8 +282,7 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
         run(std::integral_constant<bool, false>{});
       while (cs_cur < s1) end_sweep(cs_cur++);
       if (I.trace_part && w == 0 && lane == 0)
-        for (int s = s0; s < s1; ++s) I.trace_part[(size_t)item.tile16 * S + s] = strace[s % kTraceEpoch];
-      if (S == 0) break;
+        for (int s = s0; s < s1; ++s) I.trace_part[(size_t)item.tile16 * S + (s - p.s_first)] = strace[s % kTraceEpoch];
     }
 
     // write back (wave 0 holds the outputs; all waves hold identical states)
@@ -359,6 +354,8 @@ __global__ void term_reduce_multi(const InstSmall* in, int which) {
   if (I.n_mono == 0) { sf = 0.0; si = 0; }
   if (which == 0) {
     I.e_track[b] = I.integer ? (double)si : sf;
+  } else if (which == 2) {
+    I.best_track[b] = I.integer ? (double)si : sf;
   } else if (I.best_out) {
     if (I.integer)
       reinterpret_cast<long long*>(I.best_out)[b] = si;
@@ -411,37 +408,77 @@ void anneal_shape(int T, int cs_req, int* ctw, int* cs) {
   *cs = c;
 }
 
-// Enqueue the whole anneal sequence for instances [i0, i1) of the tables.
-int enqueue_anneal_seq(const AnnealTables& tb, int n_inst, int sweeps, uint64_t seed, int init_random,
-                       int prec, int ct, int nw, int item0, int nitems, int inst0, int ninst,
-                       void* stream, std::string* err) {
-  (void)n_inst;
+int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipStream_t st);
+int anneal_mask_window();
+
+// The annealing sequence of one launch plan, in three parts: random start
+// states and start energies (FP64 / int64 term sums); the sweeps (blocked
+// kernel items in windows, then per-bit slab kernel items); the FP64 rescore
+// of the best states and the per-sweep trace minima.
+int enqueue_anneal_setup(const AnnealTables& tb, const AnnealPlan& pl, void* stream, std::string* err) {
   hipStream_t st = (hipStream_t)stream;
-  const InstSmall* sm = tb.d_small + inst0;
-  if (init_random) {
+  const InstSmall* sm = tb.d_small + pl.inst0;
+  const unsigned ni = (unsigned)pl.ninst;
+  if (pl.init_random) {
     long long wb = (long long)tb.max_W * tb.max_B;
-    hipLaunchKernelGGL(init_random_multi, dim3((unsigned)((wb + 255) / 256), (unsigned)ninst), dim3(256), 0, st, sm,
-                       (unsigned long long)seed);
+    hipLaunchKernelGGL(init_random_multi, dim3((unsigned)((wb + 255) / 256), ni), dim3(256), 0, st, sm,
+                       (unsigned long long)pl.seed);
   }
   const unsigned rb = (unsigned)((tb.max_B + 255) / 256);
-  hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, (unsigned)ninst), dim3(256), 0, st, sm, 0);
-  hipLaunchKernelGGL(term_reduce_multi, dim3(rb, (unsigned)ninst), dim3(256), 0, st, sm, 0);
+  hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, ni), dim3(256), 0, st, sm, 0);
+  hipLaunchKernelGGL(term_reduce_multi, dim3(rb, ni), dim3(256), 0, st, sm, 0);
+  if (pl.cont) {
+    hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, ni), dim3(256), 0, st, sm, 2);
+    hipLaunchKernelGGL(term_reduce_multi, dim3(rb, ni), dim3(256), 0, st, sm, 2);
+  }
+  return hip_fail(hipGetLastError(), err, "anneal setup");
+}
+
+// Sweeps [s_begin, s_end) of the plan; attempt-mask row 0 is sweep mask_s0
+// and every 16-replica group has mask_rows rows.  `cont`: the best states
+// continue from an earlier part of the run.
+int enqueue_anneal_sweeps(const AnnealTables& tb, const AnnealPlan& pl, int s_begin, int s_end, int mask_s0,
+                          int mask_rows, int cont, void* stream, std::string* err) {
+  hipStream_t st = (hipStream_t)stream;
   AnnealParams ap{};
   ap.insts = tb.d_inst;
-  ap.items = tb.d_items + item0;
-  ap.n_items = nitems;
-  ap.sweeps = sweeps;
+  ap.sweeps = pl.sweeps;
+  ap.s_first = pl.s_first;
+  ap.mask_s0 = mask_s0;
+  ap.mask_rows = mask_rows;
   ap.beta = tb.d_beta;
-  ap.seed = seed;
+  ap.seed = pl.seed;
   ap.ones = tb.d_ones;
-  if (nitems > 0) {
-    int nblk = nitems < 2048 ? nitems : 2048;  // one work-group per 16 replicas, persistent beyond 2048
+  if (pl.n_blk > 0) {
+    ap.items = tb.d_items + pl.item0;
+    ap.n_items = pl.n_blk;
+    const int nblk = pl.n_blk < 2048 ? pl.n_blk : 2048;
+    const int win = pl.masked ? anneal_mask_window() : (s_end > s_begin ? s_end - s_begin : 1);
+    int s0 = s_begin;
+    do {  // at least one launch: with no sweeps it writes the start states back as the best ones
+      ap.s_begin = s0;
+      ap.s_end = s_end - s0 < win ? s_end : s0 + win;
+      ap.cont = (cont || s0 > s_begin) ? 1 : 0;
+      if (launch_anneal_block(ap, pl.prec, pl.nw_blk, nblk, st) != 0) {
+        *err = "no blocked annealer kernel for this precision / width";
+        return HOBO_ERR_UNSUPPORTED;
+      }
+      s0 += win;
+    } while (s0 < s_end);
+  }
+  if (pl.n_slab > 0) {
+    ap.items = tb.d_items + pl.item0 + pl.n_blk;
+    ap.n_items = pl.n_slab;
+    ap.s_begin = s_begin;
+    ap.s_end = s_end;
+    ap.cont = cont;
+    const int nblk = pl.n_slab < 2048 ? pl.n_slab : 2048;  // one work-group per 16 replicas, persistent beyond
     int r = -1;
-    switch (prec) {
-      case P_FP32: r = dispatch_anneal<P_FP32>(ap, ct, nw, nblk, st); break;
-      case P_BF16X2: r = dispatch_anneal<P_BF16X2>(ap, ct, nw, nblk, st); break;
-      case P_BF16X3: r = dispatch_anneal<P_BF16X3>(ap, ct, nw, nblk, st); break;
-      case P_INT8X4: r = dispatch_anneal<P_INT8X4>(ap, ct, nw, nblk, st); break;
+    switch (pl.prec) {
+      case P_FP32: r = dispatch_anneal<P_FP32>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_BF16X2: r = dispatch_anneal<P_BF16X2>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_BF16X3: r = dispatch_anneal<P_BF16X3>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_INT8X4: r = dispatch_anneal<P_INT8X4>(ap, pl.ct, pl.nw, nblk, st); break;
       default: break;
     }
     if (r != 0) {
@@ -449,12 +486,28 @@ int enqueue_anneal_seq(const AnnealTables& tb, int n_inst, int sweeps, uint64_t 
       return HOBO_ERR_UNSUPPORTED;
     }
   }
-  hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, (unsigned)ninst), dim3(256), 0, st, sm, 1);
-  hipLaunchKernelGGL(term_reduce_multi, dim3(rb, (unsigned)ninst), dim3(256), 0, st, sm, 1);
-  if (sweeps > 0)
-    hipLaunchKernelGGL(trace_reduce_multi, dim3((unsigned)((sweeps + 255) / 256), (unsigned)ninst), dim3(256), 0, st,
-                       sm, sweeps);
   return hip_fail(hipGetLastError(), err, "anneal launch");
+}
+
+int enqueue_anneal_finish(const AnnealTables& tb, const AnnealPlan& pl, void* stream, std::string* err) {
+  hipStream_t st = (hipStream_t)stream;
+  const InstSmall* sm = tb.d_small + pl.inst0;
+  const unsigned ni = (unsigned)pl.ninst;
+  const unsigned rb = (unsigned)((tb.max_B + 255) / 256);
+  hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, ni), dim3(256), 0, st, sm, 1);
+  hipLaunchKernelGGL(term_reduce_multi, dim3(rb, ni), dim3(256), 0, st, sm, 1);
+  if (pl.sweeps > 0)
+    hipLaunchKernelGGL(trace_reduce_multi, dim3((unsigned)((pl.sweeps + 255) / 256), ni), dim3(256), 0, st,
+                       sm, pl.sweeps);
+  return hip_fail(hipGetLastError(), err, "anneal finish");
+}
+
+int enqueue_anneal_seq(const AnnealTables& tb, const AnnealPlan& pl, void* stream, std::string* err) {
+  if (int s = enqueue_anneal_setup(tb, pl, stream, err)) return s;
+  if (int s = enqueue_anneal_sweeps(tb, pl, pl.s_first, pl.s_first + pl.sweeps, pl.s_first, pl.sweeps, pl.cont,
+                                    stream, err))
+    return s;
+  return enqueue_anneal_finish(tb, pl, stream, err);
 }
 
 }  // namespace hobo

@@ -330,6 +330,24 @@ __device__ inline void term_partial(const TermJob& J, int rowblock, int grp, Ter
 }
 
 
+// Arguments of the annealing kernels.  Sweep indices are global within the
+// temperature schedule (Philox counters use them); beta and trace rows are
+// relative to the call's first sweep; a launch runs sweeps [s_begin, s_end).
+struct AnnealParams {
+  const AnnealInstDev* insts;
+  const AnnealItem* items;
+  int n_items;
+  int sweeps;                 // sweeps of the call (rows of beta and of the trace)
+  int s_first;                // global index of the call's first sweep (row 0)
+  int s_begin, s_end;         // global sweeps of this launch
+  int cont;                   // 1: best state / energy continue from best_x / best_track
+  int mask_s0;                // sweep of attempt-mask row 0
+  int mask_rows;              // attempt-mask rows per 16-replica tile
+  const double* beta;         // [S] inverse temperatures
+  unsigned long long seed;
+  const unsigned char* ones;  // a device byte equal to 1 (attempt flag without masks)
+};
+
 inline int hip_fail(hipError_t e, std::string* err, const char* what) {
   if (e == hipSuccess) return HOBO_OK;
   *err = std::string(what) + ": " + hipGetErrorString(e);

@@ -2,6 +2,8 @@
 // of the HOBO engine.  Nothing here is part of the public C-ABI.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -21,7 +23,7 @@ constexpr int kTileCols = 16;      // MFMA 16x16 output tile width
 enum Prec : int { P_FP32 = 0, P_BF16X2 = 1, P_BF16X3 = 2, P_INT8X4 = 3, P_FP64 = 4 };
 
 // layouts a coefficient matrix can be packed for
-enum Mode : int { M_FIELDS = 0, M_ENERGY = 1, M_SLABS = 2 };
+enum Mode : int { M_FIELDS = 0, M_ENERGY = 1, M_SLABS = 2, M_BLOCKS = 3 };
 
 // runs per chunk: one MFMA K-step covers 4 runs (32 rows) for FP32/BF16 and
 // 8 runs (64 rows) for INT8
@@ -63,6 +65,25 @@ struct SlabMeta {     // annealer: per-variable slab of the local field
   int64_t a_i;
 };
 
+// Blocked annealer: variables in blocks of 16.  For block q (variables
+// J = 16q .. 16q+15) list 0 is the field matrix of the block's 16 columns
+// (rows: monomials of order <= k-1), lists 1..8 are the pair matrices of the
+// 120 pairs (a, b) of J, 16 pairs per list (rows: monomials of order <= k-2,
+// entry w_{row u {a, b}}), and the block's 16x16x16 table holds the order-3
+// coefficients w_{abc} of triples inside J.  Every chunk of these lists has
+// exactly one tile: chunk c's tile is tile 1 + c of the tile buffer.
+constexpr int kBlockBits = 16;
+constexpr int kBlockLists = 9;
+constexpr int kPairTiles = 8;
+struct BlockMeta {
+  uint32_t chunk0[kBlockLists];   // first chunk of each list
+  uint32_t nchunks[kBlockLists];  // chunks of each list
+  uint32_t nbits;                 // variables in the block (16, fewer in the last)
+  uint32_t npt;                   // pair lists in use (ceil(C(nbits,2) / 16))
+};
+// pair (a, b), a < b < 16, of a block -> its column among the 120 pair columns
+__host__ __device__ inline int pair_col(int a, int b) { return b * (b - 1) / 2 + a; }
+
 // Device-resident packed matrix for one (mode, precision).
 struct Packed {
   int mode = 0, prec = 0;
@@ -73,6 +94,9 @@ struct Packed {
   ChunkMeta* d_chunks = nullptr;
   uint64_t* d_runs = nullptr;
   SlabMeta* d_slabs = nullptr;  // slabs mode only, [n_vars]
+  BlockMeta* d_blocks = nullptr;  // blocks mode only, [nblocks]
+  float* d_triples = nullptr;     // blocks mode only, [nblocks][16][16][16] w_{abc} at [c][a][b]
+  int nblocks = 0;
   std::vector<ChunkMeta> h_chunks;
   size_t bytes = 0;
   ~Packed();
@@ -110,7 +134,7 @@ struct Tensor {
   std::mutex mu;
   std::map<int, std::unique_ptr<Packed>> packed;  // key = mode*16 + prec
   std::unique_ptr<TermsDev> terms;
-  float* d_row_norm = nullptr;
+  double* d_row_norm = nullptr;  // device copy of row_norm (uploaded on first use)
   ~Tensor();
   int n_mono() const { return (int)(mono_ptr.size() - 1); }
 };
@@ -129,6 +153,23 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
 // pack.cpp -- build (once) the packed layout; returns a status code
 int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err);
 int get_terms(Tensor* t, TermsDev** out, std::string* err);
+int get_row_norms(Tensor* t, const double** out, std::string* err);
+
+// mlp_kernels.hip -- the learned flip proposal
+int mlp_forward(const float* params, const float* feats, long long M, float* logits, hipStream_t st,
+                std::string* err);
+size_t mlp_train_workspace(int batch);
+int mlp_train_step(float* state, const float* feats, const float* labels, long long m0, int mb, float lr,
+                   float beta1, float beta2, float eps, float bc1, float bc2, float* part, float* loss_out,
+                   hipStream_t st, std::string* err);
+int mlp_grad(const float* params, const float* feats, const float* labels, int mb, float* part, float* grad,
+             float* loss_out, hipStream_t st, std::string* err);
+int proposal_features(const unsigned long long* x, const unsigned long long* xa, long long B, int N, const void* de,
+                      int de_int, double beta, const double* rnorm, float* feats, float* labels, hipStream_t st,
+                      std::string* err);
+int proposal_masks(const float* params, const unsigned long long* x, long long B, int N, const void* de, int de_int,
+                   double beta, const double* rnorm, float lthr, double p_floor, unsigned long long seed,
+                   unsigned long long inst, int s0, int nsw, unsigned char* mask, hipStream_t st, std::string* err);
 
 // kernels.hip -- launchers (return hipError_t as int)
 struct EvalArgs {
@@ -176,6 +217,10 @@ struct AnnealInstDev {       // per-instance view of the annealing kernel
   unsigned long long inst_id;
   unsigned n_tiles;            // tiles stored in the packed buffer
   unsigned pad2;
+  const BlockMeta* blocks;     // blocked layout: [nblocks]
+  const float* triples;        // blocked layout: [nblocks][16][16][16]
+  int nblocks;
+  int pad3;
 };
 struct AnnealItem { int inst; int tile16; };  // 16 replicas of one instance
 
@@ -190,6 +235,7 @@ struct InstSmall {            // per-instance view for the setup / finish kernel
   unsigned long long* x;
   unsigned long long* best_x;
   double* e_track;
+  double* best_track;
   void* best_out;             // double* or long long*, already offset
   const double* trace_part;   // [ntiles16][S]
   double* trace_out;          // [S] or null
@@ -217,8 +263,25 @@ void anneal_shape(int T, int cs_req, int* ctw, int* cs);
 // launch timing (kernels: 0 = annealer, 1 = fields, 2 = energy)
 void timing_enable(int on);
 int timing_read(int kernel, double* total_ms, int64_t* launches);
-int enqueue_anneal_seq(const AnnealTables& tb, int n_inst, int sweeps, uint64_t seed, int init_random,
-                       int prec, int ct, int nw, int item0, int nitems, int inst0, int ninst,
-                       void* stream, std::string* err);
+// One launch sequence of hobo_anneal_batch: items [item0, item0 + n_blk) run
+// the blocked kernel, the next n_slab items the per-bit slab kernel.
+struct AnnealPlan {
+  int sweeps = 0;       // sweeps of the call
+  int s_first = 0;      // global index of its first sweep
+  uint64_t seed = 0;
+  int init_random = 0;
+  int cont = 0;         // best state continues from best_x (rescored at the start)
+  int masked = 0;       // attempt masks present
+  int prec = 0;
+  int ct = 1, nw = 1;   // slab kernel: column tiles per wave, waves per work-group
+  int nw_blk = 4;       // blocked kernel: waves per work-group
+  int item0 = 0, n_blk = 0, n_slab = 0;
+  int inst0 = 0, ninst = 0;
+};
+int enqueue_anneal_seq(const AnnealTables& tb, const AnnealPlan& pl, void* stream, std::string* err);
+int enqueue_anneal_setup(const AnnealTables& tb, const AnnealPlan& pl, void* stream, std::string* err);
+int enqueue_anneal_sweeps(const AnnealTables& tb, const AnnealPlan& pl, int s_begin, int s_end, int mask_s0,
+                          int mask_rows, int cont, void* stream, std::string* err);
+int enqueue_anneal_finish(const AnnealTables& tb, const AnnealPlan& pl, void* stream, std::string* err);
 
 }  // namespace hobo

@@ -41,6 +41,8 @@ Packed::~Packed() {
   if (d_chunks) (void)hipFree(d_chunks);
   if (d_runs) (void)hipFree(d_runs);
   if (d_slabs) (void)hipFree(d_slabs);
+  if (d_blocks) (void)hipFree(d_blocks);
+  if (d_triples) (void)hipFree(d_triples);
 }
 TermsDev::~TermsDev() {
   if (d_rec) (void)hipFree(d_rec);
@@ -159,7 +161,7 @@ struct PackOut {
 // tiles in precision `prec`.  When `segments` is set the runs of each degree
 // start a new chunk and the chunk that closes a degree carries seg_end.
 int pack_runs(const RunMat& rm, const std::vector<int>& ord, int prec, bool segments, int n_col_tiles,
-              PackOut* po, std::string* err) {
+              PackOut* po, std::string* err, bool all_tiles = false) {
   const int rpc = runs_per_chunk(prec);
   const int n = rm.n;
   // padded run sequence (-1 = null run) and per-run order of its degree
@@ -202,6 +204,10 @@ int pack_runs(const RunMat& rm, const std::vector<int>& ord, int prec, bool segm
       }
     }
     if (t_hi <= t_lo) t_lo = t_hi = 0;
+    if (all_tiles) {  // store every column tile, zero ones included
+      t_lo = 0;
+      t_hi = n_col_tiles;
+    }
     ChunkMeta cm{};
     cm.tile_off = (uint32_t)(po->tiles.size() / (size_t)tb);
     cm.t_lo = (uint8_t)t_lo;
@@ -347,6 +353,88 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
     st = pack_runs(rm, run_order(rm), prec, mode == M_FIELDS, n_col_tiles, &po, err);
     if (st) return st;
     pk->nchunks = (int)po.chunks.size();
+  } else if (mode == M_BLOCKS) {
+    if (t->order > 3) {
+      *err = "the blocked annealing layout covers orders up to 3";
+      return HOBO_ERR_UNSUPPORTED;
+    }
+    if (prec == P_INT8X4) {
+      *err = "the blocked annealing layout has no INT8X4 form";
+      return HOBO_ERR_UNSUPPORTED;
+    }
+    const int nb = (n + kBlockBits - 1) / kBlockBits;
+    std::vector<std::vector<int>> touch((size_t)nb);  // monomials with a variable in each block
+    for (int m = 0; m < nm; ++m) {
+      int last = -1;
+      for (int64_t p = t->mono_ptr[m]; p < t->mono_ptr[m + 1]; ++p) {
+        int q = t->mono_idx[p] / kBlockBits;
+        if (q != last) touch[(size_t)q].push_back(m);
+        last = q;
+      }
+    }
+    std::vector<BlockMeta> bm((size_t)nb);
+    std::vector<float> tri((size_t)nb * 4096, 0.0f);
+    for (int q = 0; q < nb; ++q) {
+      const int j0 = q * kBlockBits;
+      const int nbits = std::min(kBlockBits, n - j0);
+      const int npairs = nbits * (nbits - 1) / 2;
+      const int npt = (npairs + kTileCols - 1) / kTileCols;
+      RunMat rg;
+      rg.n = kTileCols;
+      rg.integer = t->integer;
+      std::vector<RunMat> rh((size_t)kPairTiles);
+      for (auto& r : rh) {
+        r.n = kTileCols;
+        r.integer = t->integer;
+      }
+      for (int m : touch[(size_t)q]) {
+        const uint8_t* s = t->mono_idx.data() + t->mono_ptr[m];
+        const int len = (int)(t->mono_ptr[m + 1] - t->mono_ptr[m]);
+        const double wf = t->w_f[m];
+        const int64_t wi = t->integer ? t->w_i[m] : 0;
+        int in[kMaxOrder], nin = 0;  // positions of s inside the block
+        for (int a = 0; a < len; ++a)
+          if (s[a] >= j0 && s[a] < j0 + kBlockBits) in[nin++] = a;
+        for (int u = 0; u < nin; ++u) {  // field of variable s[in[u]]: row S minus it
+          int nr = 0;
+          for (int b = 0; b < len; ++b)
+            if (b != in[u]) rest[nr++] = s[b];
+          scatter(rg, rest, nr, s[in[u]] - j0, wf, wi);
+        }
+        for (int u = 0; u < nin; ++u)
+          for (int v = u + 1; v < nin; ++v) {  // coupling of the pair: row S minus both
+            int nr = 0;
+            for (int b = 0; b < len; ++b)
+              if (b != in[u] && b != in[v]) rest[nr++] = s[b];
+            const int pc = pair_col(s[in[u]] - j0, s[in[v]] - j0);
+            scatter(rh[(size_t)(pc / kTileCols)], rest, nr, pc % kTileCols, wf, wi);
+          }
+        if (len == 3 && nin == 3) {  // triple inside the block, stored at every ordering
+          const int v3[3] = {s[0] - j0, s[1] - j0, s[2] - j0};
+          const int pm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+          for (auto& o : pm)
+            tri[(size_t)q * 4096 + (size_t)v3[o[0]] * 256 + (size_t)v3[o[1]] * 16 + (size_t)v3[o[2]]] = (float)wf;
+        }
+      }
+      BlockMeta& b = bm[(size_t)q];
+      b.nbits = (uint32_t)nbits;
+      b.npt = (uint32_t)npt;
+      for (int li = 0; li < kBlockLists; ++li) {
+        b.chunk0[li] = (uint32_t)po.chunks.size();
+        if (li == 0 || li - 1 < npt) {
+          RunMat& r = li == 0 ? rg : rh[(size_t)(li - 1)];
+          st = pack_runs(r, run_order(r), prec, false, 1, &po, err, true);
+          if (st) return st;
+        }
+        b.nchunks[li] = (uint32_t)po.chunks.size() - b.chunk0[li];
+      }
+    }
+    pk->nchunks = (int)po.chunks.size();
+    pk->nblocks = nb;
+    st = upload(bm, &pk->d_blocks, &pk->bytes, err);
+    if (st) return st;
+    st = upload(tri, &pk->d_triples, &pk->bytes, err);
+    if (st) return st;
   } else {  // M_SLABS: one triangular matrix per variable i
     // monomials containing each variable
     std::vector<std::vector<int>> inc((size_t)n);
@@ -409,6 +497,22 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
   if (st) return st;
   *out = pk.get();
   t->packed.emplace(key, std::move(pk));
+  return HOBO_OK;
+}
+
+int get_row_norms(Tensor* t, const double** out, std::string* err) {
+  std::lock_guard<std::mutex> lock(t->mu);
+  if (!t->d_row_norm) {
+    size_t bytes = 0;
+    double* d = nullptr;
+    int st = upload(t->row_norm, &d, &bytes, err);
+    if (st) {
+      if (d) (void)hipFree(d);
+      return st;
+    }
+    t->d_row_norm = d;
+  }
+  *out = t->d_row_norm;
   return HOBO_OK;
 }
 

@@ -20,14 +20,20 @@ COEFF_INT64, COEFF_F64 = 0, 1
 PREC_FP32, PREC_BF16X2, PREC_BF16X3, PREC_INT8X4, PREC_FP64 = range(5)
 PREC_NAMES = {"fp32": PREC_FP32, "bf16x2": PREC_BF16X2, "bf16x3": PREC_BF16X3, "int8x4": PREC_INT8X4, "fp64": PREC_FP64}
 INIT_RANDOM, INIT_GIVEN = 0, 1
-PROPOSAL_METROPOLIS, PROPOSAL_MASKED = 0, 1
+PROPOSAL_METROPOLIS, PROPOSAL_MASKED, PROPOSAL_LEARNED = 0, 1, 2
+ANNEAL_AUTO, ANNEAL_SLABS, ANNEAL_BLOCKS = 0, 1, 2
 LAUNCH_PER_INSTANCE, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2
 FN_ENERGY, FN_FIELDS, FN_ANNEAL = 1, 2, 4
+MLP_HIDDEN, MLP_FEATURES = 256, 3
+MLP_PARAMS = MLP_FEATURES * MLP_HIDDEN + 2 * MLP_HIDDEN + 1
+MLP_ROW = 1284
+MLP_STATE = 3 * MLP_ROW
 
 EXPORTS = [
     "hobo_build_tensor", "hobo_free_tensor", "hobo_tensor_info_get", "hobo_tensor_monomials",
     "hobo_tensor_export_dense", "hobo_tensor_prepare", "hobo_energy", "hobo_local_fields",
     "hobo_anneal_batch", "hobo_timing_enable", "hobo_timing_read", "hobo_last_error", "hobo_version",
+    "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features",
 ]
 
 
@@ -47,7 +53,15 @@ class AnnealParams(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("precision", ctypes.c_int32), ("t_start", ctypes.c_double),
                 ("t_end", ctypes.c_double), ("seed", ctypes.c_uint64), ("init", ctypes.c_int32),
                 ("proposal", ctypes.c_int32), ("attempt", ctypes.c_void_p), ("waves_per_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("algorithm", ctypes.c_int32), ("first_sweep", ctypes.c_int32), ("schedule_sweeps", ctypes.c_int32),
+                ("continue_best", ctypes.c_int32), ("refresh", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("tau", ctypes.c_float), ("p_floor", ctypes.c_float)]
+
+
+class MlpTrainParams(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("step0", ctypes.c_int64)]
 
 
 def _load():
@@ -64,6 +78,10 @@ def _load():
     lib.hobo_energy.argtypes = [P, P, i64, i32, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
+    lib.hobo_mlp_forward.argtypes = [P, P, i64, P, P]
+    lib.hobo_mlp_grad.argtypes = [P, P, P, i64, P, P, P]
+    lib.hobo_mlp_train.argtypes = [P, P, P, i64, ctypes.POINTER(MlpTrainParams), P, P]
+    lib.hobo_proposal_features.argtypes = [P, P, P, i64, P, ctypes.c_double, P, P, P]
     lib.hobo_timing_enable.argtypes = [i32]
     lib.hobo_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
@@ -205,8 +223,11 @@ def local_fields(t: Tensor, x_bits, B: int, precision: int, de_out, e_out=None, 
 
 def anneal_batch(tensors, replicas, x_inout, best_x_out, best_e_out, *, sweeps: int, t_start: float, t_end: float,
                  seed: int, precision: int = PREC_FP32, init: int = INIT_RANDOM, attempt=None, trace_out=None,
-                 launch_mode: int = LAUNCH_PERSISTENT, waves_per_block: int = 0, stream=None):
-    """hobo_anneal_batch over one or several instances (concatenated buffers)."""
+                 launch_mode: int = LAUNCH_PERSISTENT, waves_per_block: int = 0, algorithm: int = ANNEAL_AUTO,
+                 first_sweep: int = 0, schedule_sweeps: int = 0, continue_best: bool = False, mlp=None,
+                 tau: float = 0.5, p_floor: float = 0.0, refresh: int = 1, stream=None):
+    """hobo_anneal_batch over one or several instances (concatenated buffers).
+    ``attempt`` selects MASKED, ``mlp`` (device FP32 parameters) LEARNED."""
     if isinstance(tensors, Tensor):
         tensors = [tensors]
     n = len(tensors)
@@ -220,6 +241,12 @@ def anneal_batch(tensors, replicas, x_inout, best_x_out, best_e_out, *, sweeps: 
         raise ValueError("best_e_out too small")
     if trace_out is not None and trace_out.numel() < n * sweeps:
         raise ValueError("trace_out too small")
+    if attempt is not None:
+        need = sum(((int(b) + 15) // 16) * int(sweeps) * t.n_vars for t, b in zip(tensors, reps))
+        if attempt.numel() < need or attempt.element_size() != 1:
+            raise ValueError(f"attempt masks must hold {need} bytes")
+    if mlp is not None and (mlp.numel() < MLP_PARAMS or mlp.element_size() != 4):
+        raise ValueError(f"mlp must hold {MLP_PARAMS} FP32 values")
     handles = (ctypes.c_void_p * n)(*[t.handle.value for t in tensors])
     p = AnnealParams()
     p.sweeps = int(sweeps)
@@ -228,12 +255,66 @@ def anneal_batch(tensors, replicas, x_inout, best_x_out, best_e_out, *, sweeps: 
     p.t_end = float(t_end)
     p.seed = int(seed)
     p.init = int(init)
-    p.proposal = PROPOSAL_MASKED if attempt is not None else PROPOSAL_METROPOLIS
+    p.proposal = PROPOSAL_MASKED if attempt is not None else (PROPOSAL_LEARNED if mlp is not None else
+                                                               PROPOSAL_METROPOLIS)
     p.attempt = _dev_ptr(attempt) if attempt is not None else None
     p.waves_per_block = int(waves_per_block)
+    p.algorithm = int(algorithm)
+    p.first_sweep = int(first_sweep)
+    p.schedule_sweeps = int(schedule_sweeps)
+    p.continue_best = 1 if continue_best else 0
+    p.refresh = int(refresh)
+    p.mlp = _dev_ptr(mlp) if mlp is not None else None
+    p.tau = float(tau)
+    p.p_floor = float(p_floor)
     _check(lib.hobo_anneal_batch(handles, n, _np_ptr(reps), ctypes.byref(p), _dev_ptr(x_inout), _dev_ptr(best_x_out),
                                  _dev_ptr(best_e_out), _dev_ptr(trace_out) if trace_out is not None else None,
                                  int(launch_mode), _stream(stream)))
+
+
+def mlp_forward(params, feats, logits_out, stream=None):
+    """hobo_mlp_forward: logits of feats [M][3] (device FP32)."""
+    m = feats.numel() // 3
+    if feats.numel() != 3 * m or logits_out.numel() < m or params.numel() < MLP_PARAMS:
+        raise ValueError("feats must be [M][3], logits_out [M], params [1281]")
+    _check(lib.hobo_mlp_forward(_dev_ptr(params), _dev_ptr(feats), m, _dev_ptr(logits_out), _stream(stream)))
+
+
+def mlp_grad(params, feats, labels, grad_out, loss_out=None, stream=None):
+    """hobo_mlp_grad: mean-BCE gradient over all samples (device FP32)."""
+    m = feats.numel() // 3
+    if feats.numel() != 3 * m or labels.numel() < m or grad_out.numel() < MLP_PARAMS:
+        raise ValueError("feats must be [M][3], labels [M], grad_out [1281]")
+    _check(lib.hobo_mlp_grad(_dev_ptr(params), _dev_ptr(feats), _dev_ptr(labels), m, _dev_ptr(grad_out),
+                             _dev_ptr(loss_out) if loss_out is not None else None, _stream(stream)))
+
+
+def mlp_train(state, feats, labels, *, batch: int, epochs: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8, step0: int = 0, loss_trace=None, stream=None):
+    """hobo_mlp_train on a device FP32 state [params | m | v] (rows of 1284)."""
+    m = feats.numel() // 3
+    if feats.numel() != 3 * m or labels.numel() < m or state.numel() < MLP_STATE:
+        raise ValueError("feats must be [M][3], labels [M], state [3 * 1284]")
+    steps = epochs * ((m + batch - 1) // batch)
+    if loss_trace is not None and loss_trace.numel() < steps:
+        raise ValueError(f"loss_trace must hold {steps} values")
+    tp = MlpTrainParams(int(batch), int(epochs), float(lr), float(beta1), float(beta2), float(eps), int(step0))
+    _check(lib.hobo_mlp_train(_dev_ptr(state), _dev_ptr(feats), _dev_ptr(labels), m, ctypes.byref(tp),
+                              _dev_ptr(loss_trace) if loss_trace is not None else None, _stream(stream)))
+
+
+def proposal_features(t: Tensor, x_bits, B: int, de, beta: float, feats_out, x_after=None, labels_out=None,
+                      stream=None):
+    """hobo_proposal_features: feats_out [B][N][3] (and transition labels)."""
+    _check_bits(t, x_bits, B)
+    n = t.n_vars
+    if feats_out.numel() < 3 * B * n or de.numel() < B * n:
+        raise ValueError("feats_out must hold B*N*3 values and de B*N")
+    if labels_out is not None and (x_after is None or labels_out.numel() < B * n):
+        raise ValueError("labels need x_after and B*N values")
+    _check(lib.hobo_proposal_features(t.handle, _dev_ptr(x_bits), _dev_ptr(x_after) if x_after is not None else None,
+                                      int(B), _dev_ptr(de), float(beta), _dev_ptr(feats_out),
+                                      _dev_ptr(labels_out) if labels_out is not None else None, _stream(stream)))
 
 
 KERNEL_ANNEAL, KERNEL_FIELDS, KERNEL_ENERGY = 0, 1, 2

@@ -21,23 +21,27 @@ def env():
     return hobo, torch
 
 
-def run_gpu(env, tensors, reps, sweeps, t0, t1, seed, prec, init_bits=None, attempt=None, mode=1, nw=0):
+def run_gpu(env, tensors, reps, sweeps, t0, t1, seed, prec, init_bits=None, attempt=None, mode=1, nw=0, algo=0,
+            first=0, total=0, cont=False, x=None, bx=None):
     hobo, torch = env
     if not isinstance(tensors, list):
         tensors, reps = [tensors], [reps]
     words = sum(((t.n_vars + 63) // 64) * b for t, b in zip(tensors, reps))
-    if init_bits is not None:
-        x = hobo.bits_to_device(np.concatenate([np.asarray(b).reshape(-1) for b in init_bits]))
-    else:
-        x = torch.zeros(words, dtype=torch.int64, device="cuda")
-    bx = torch.zeros(words, dtype=torch.int64, device="cuda")
+    if x is None:
+        if init_bits is not None:
+            x = hobo.bits_to_device(np.concatenate([np.asarray(b).reshape(-1) for b in init_bits]))
+        else:
+            x = torch.zeros(words, dtype=torch.int64, device="cuda")
+    if bx is None:
+        bx = torch.zeros(words, dtype=torch.int64, device="cuda")
     integer = all(t.integer for t in tensors)
     be = torch.zeros(sum(reps), dtype=torch.int64 if integer else torch.float64, device="cuda")
     tr = torch.zeros(len(tensors) * max(sweeps, 1), dtype=torch.float64, device="cuda")
     att = None if attempt is None else torch.from_numpy(np.ascontiguousarray(attempt, dtype=np.uint8)).cuda()
     hobo.anneal_batch(tensors, reps, x, bx, be, sweeps=sweeps, t_start=t0, t_end=t1, seed=seed, precision=prec,
-                      init=hobo.INIT_GIVEN if init_bits is not None else hobo.INIT_RANDOM, attempt=att,
-                      trace_out=tr, launch_mode=mode, waves_per_block=nw)
+                      init=hobo.INIT_GIVEN if (init_bits is not None or first > 0) else hobo.INIT_RANDOM,
+                      attempt=att, trace_out=tr, launch_mode=mode, waves_per_block=nw, algorithm=algo,
+                      first_sweep=first, schedule_sweeps=total, continue_best=cont)
     torch.cuda.synchronize()
     out = []
     xo, bo = hobo.bits_to_host(x), hobo.bits_to_host(bx)
@@ -49,6 +53,8 @@ def run_gpu(env, tensors, reps, sweeps, t0, t1, seed, prec, init_bits=None, atte
                         best_e=beo[ro:ro + b], trace=tro[j * sweeps:(j + 1) * sweeps]))
         wo += w * b
         ro += b
+    for d in out:
+        d["x_dev"], d["bx_dev"] = x, bx
     return out
 
 
@@ -70,15 +76,72 @@ def _int_instance(seed, n, k, lo=-5, hi=5, dens=0.7):
     return W.subsets_to_terms(n, subs, co, True)
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3])
-def test_trajectory_identity_int3(env, prec):
+SLABS, BLOCKS = 1, 2
+
+
+@pytest.mark.parametrize("prec,algo", [(0, SLABS), (1, SLABS), (2, SLABS), (3, SLABS), (0, BLOCKS), (1, BLOCKS),
+                                       (2, BLOCKS)])
+def test_trajectory_identity_int3(env, prec, algo):
     hobo, _ = env
     terms = W.cfg_int3(seed=4)
     c = oracle.canonicalize(terms)
     t = hobo.Tensor.from_terms(terms)
-    g = run_gpu(env, t, 100, 40, 5.0, 0.05, seed=123, prec=prec)[0]
+    g = run_gpu(env, t, 100, 40, 5.0, 0.05, seed=123, prec=prec, algo=algo)[0]
     o = oracle.anneal(c, 100, 40, 5.0, 0.05, seed=123)
     assert_same(g, o)
+
+
+@pytest.mark.parametrize("n,k,dens,nw", [(5, 3, 1.0, 1), (16, 2, 1.0, 2), (37, 3, 0.6, 4), (64, 3, 0.25, 8),
+                                         (130, 2, 0.4, 4), (100, 1, 1.0, 2), (48, 3, 0.5, 1)])
+def test_blocked_trajectory_identity(env, n, k, dens, nw):
+    """The blocked annealer (fields and pair couplings per 16-bit block, the
+    block's sixteen decisions resolved in registers) runs the oracle's chain:
+    ragged last blocks, every order up to 3, one to eight waves."""
+    hobo, _ = env
+    terms = _int_instance(100 + n, n, k, lo=-4, hi=4, dens=dens)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    g = run_gpu(env, t, 37, 12, 4.0, 0.1, seed=77, prec=1, algo=BLOCKS, nw=nw)[0]
+    o = oracle.anneal(c, 37, 12, 4.0, 0.1, seed=77)
+    assert_same(g, o)
+
+
+def test_blocked_masks_across_windows(env):
+    """Attempt masks with more sweeps than one masked launch covers (the
+    blocked kernel runs masked calls in windows of 64 sweeps); whole blocks
+    and whole sweeps masked out for some groups."""
+    hobo, _ = env
+    n, B, S = 40, 50, 150
+    terms = _int_instance(31, n, 3, lo=-3, hi=3, dens=0.5)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    rng = np.random.default_rng(5)
+    mask = (rng.random(((B + 15) // 16, S, n)) < 0.5).astype(np.uint8)
+    mask[0, :, 16:32] = 0       # a whole block never attempted by group 0
+    mask[1, 70:90, :] = 0       # whole sweeps skipped by group 1
+    x0 = W.pack_bits(W.random_states(n, B, seed=6))
+    for algo in (SLABS, BLOCKS):
+        g = run_gpu(env, t, B, S, 3.0, 0.2, seed=8, prec=0, init_bits=[x0], attempt=mask, algo=algo)[0]
+        o = oracle.anneal(c, B, S, 3.0, 0.2, seed=8, init_bits=x0, attempt=mask)
+        assert_same(g, o)
+
+
+@pytest.mark.parametrize("algo", [SLABS, BLOCKS])
+def test_schedule_split_into_calls(env, algo):
+    """Sweeps 0..11 and 12..29 of a 30-sweep schedule in two calls (the
+    second continuing the state and the best state) equal one 30-sweep call."""
+    hobo, _ = env
+    terms = _int_instance(41, 24, 3)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    o = oracle.anneal(c, 33, 30, 4.0, 0.05, seed=9)
+    a = run_gpu(env, t, 33, 12, 4.0, 0.05, seed=9, prec=0, algo=algo, total=30)[0]
+    b = run_gpu(env, t, 33, 18, 4.0, 0.05, seed=9, prec=0, algo=algo, first=12, total=30, cont=True,
+                x=a["x_dev"], bx=a["bx_dev"])[0]
+    np.testing.assert_array_equal(b["final_bits"], o["final_bits"])
+    np.testing.assert_array_equal(b["best_bits"], o["best_bits"])
+    np.testing.assert_array_equal(b["best_e"], o["best_e"])
+    np.testing.assert_array_equal(np.concatenate([a["trace"], b["trace"]]), o["trace"])
 
 
 @pytest.mark.parametrize("make,prec", [(W.paper_seating, 0), (W.paper_pythagorean, 3), (W.paper_tsp_intenc, 3),

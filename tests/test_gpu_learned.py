@@ -1,0 +1,120 @@
+"""The LEARNED proposal inside hobo_anneal_batch against the oracle's
+composition of the same steps: fields of the current states, features,
+network logits (FP64 oracle), tile attempt masks with floor draws, then the
+Metropolis sweeps of the segment with those masks.  The logit threshold is
+chosen away from every logit the run meets, so both sides take the same
+attempt decisions and the chains are identical on integer instances."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.mlp as M
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2407_19987_amd import hobo
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return hobo, torch
+
+
+def oracle_learned(c, params, B, S, t0, t1, seed, tau, p_floor, refresh, x0):
+    n = c.n_vars
+    betas = 1.0 / oracle.schedule(t0, t1, S)
+    x = np.array(x0, dtype=np.uint64)
+    best_bits = x.copy()
+    best_e = oracle.energy(c, x)
+    trace, margins = [], []
+    thr = math.log(tau / (1 - tau)) if 0 < tau < 1 else (-math.inf if tau <= 0 else math.inf)
+    for s0 in range(0, S, refresh):
+        ln = min(refresh, S - s0)
+        ft = M.features(c, x, betas[s0])
+        lg = M.forward(params, ft.reshape(-1, 3)).reshape(B, n)
+        tmax = np.stack([lg[16 * t:16 * t + 16].max(axis=0) for t in range((B + 15) // 16)])
+        margins.append(np.abs(tmax - thr).min() if math.isfinite(thr) else math.inf)
+        mask = M.proposal_mask(lg, list(range(s0, s0 + ln)), tau, p_floor, seed)
+        r = oracle.anneal(c, B, ln, t0, t1, seed, init_bits=x, attempt=mask, first_sweep=s0, schedule_sweeps=S)
+        better = r["best_e"] < best_e
+        best_bits[:, better] = r["best_bits"][:, better]
+        trace.extend(np.minimum(best_e.min(), r["trace"]))
+        best_e = np.where(better, r["best_e"], best_e)
+        x = r["final_bits"]
+    return dict(final_bits=x, best_bits=best_bits, best_e=best_e, trace=np.array(trace)), min(margins)
+
+
+def run_gpu(env, t, params, B, S, t0, t1, seed, tau, p_floor, refresh, x0, algo=0):
+    hobo, torch = env
+    x = hobo.bits_to_device(x0)
+    bx = torch.zeros_like(x)
+    be = torch.zeros(B, dtype=torch.int64, device="cuda")
+    tr = torch.zeros(S, dtype=torch.float64, device="cuda")
+    mlp = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda()
+    hobo.anneal_batch(t, B, x, bx, be, sweeps=S, t_start=t0, t_end=t1, seed=seed, precision=hobo.PREC_FP32,
+                      init=hobo.INIT_GIVEN, trace_out=tr, mlp=mlp, tau=tau, p_floor=p_floor, refresh=refresh,
+                      algorithm=algo)
+    torch.cuda.synchronize()
+    return dict(final_bits=hobo.bits_to_host(x).reshape(x0.shape), best_bits=hobo.bits_to_host(bx).reshape(x0.shape),
+                best_e=be.cpu().numpy(), trace=tr.cpu().numpy())
+
+
+def _params(seed):
+    p = W.mlp_init(seed)
+    p[M.OFF_B1:M.OFF_W2] = np.random.default_rng(seed).normal(0, 0.5, M.HIDDEN)
+    return p
+
+
+def _same(g, o):
+    for k in ("final_bits", "best_bits", "best_e", "trace"):
+        np.testing.assert_array_equal(g[k], o[k], err_msg=k)
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+def test_learned_extremes_reduce_to_plain_and_frozen(env, algo):
+    hobo, _ = env
+    terms = W.cfg_int3(seed=3, n=20)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    B, S = 40, 9
+    x0 = W.pack_bits(W.random_states(20, B, seed=4))
+    p = _params(5)
+    plain = oracle.anneal(c, B, S, 3.0, 0.2, seed=6, init_bits=x0)
+    for tau, pf in ((0.0, 0.0), (1.0, 1.0)):  # every bit attempted: plain Metropolis
+        _same(run_gpu(env, t, p, B, S, 3.0, 0.2, 6, tau, pf, 4, x0, algo), plain)
+    g = run_gpu(env, t, p, B, S, 3.0, 0.2, 6, 1.0, 0.0, 4, x0, algo)  # nothing attempted
+    np.testing.assert_array_equal(g["final_bits"], x0)
+    np.testing.assert_array_equal(g["best_e"], oracle.energy(c, x0))
+
+
+@pytest.mark.parametrize("algo,n,refresh,p_floor", [(2, 20, 4, 0.3), (1, 20, 3, 0.0), (2, 37, 5, 0.1),
+                                                    (1, 12, 2, 0.2)])
+def test_learned_matches_oracle(env, algo, n, refresh, p_floor):
+    hobo, _ = env
+    terms = W.cfg_int3(seed=n, n=n) if n != 12 else W.paper_pythagorean()
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    B, S, t0, t1, seed = 40, 11, 3.0, 0.2, 8
+    x0 = W.pack_bits(W.random_states(c.n_vars, B, seed=9))
+    p = _params(10 + n)
+    if c.order > 3 and algo == 2:
+        pytest.skip("the blocked annealer covers orders up to 3")
+    # a threshold in a gap of the logits the oracle run meets
+    for q in (0.5, 0.35, 0.65, 0.2, 0.8, 0.45, 0.55):
+        ft = M.features(c, x0, 1.0 / t0)
+        lg = np.sort(M.forward(p, ft.reshape(-1, 3)))
+        thr = float(np.quantile(lg, q))
+        tau = 1.0 / (1.0 + math.exp(-thr)) if abs(thr) < 30 else 0.5
+        o, margin = oracle_learned(c, p, B, S, t0, t1, seed, tau, p_floor, refresh, x0)
+        if margin > 1e-3:
+            break
+    else:
+        pytest.fail("no logit gap found for the attempt threshold")
+    g = run_gpu(env, t, p, B, S, t0, t1, seed, tau, p_floor, refresh, x0, algo)
+    _same(g, o)

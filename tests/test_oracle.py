@@ -309,3 +309,19 @@ def test_anneal_given_init_and_determinism():
     z = oracle.anneal(c, 32, 0, 3.0, 0.1, seed=9, init_bits=x0)
     np.testing.assert_array_equal(z["final_bits"], x0)
     np.testing.assert_array_equal(z["best_e"], oracle.energy(c, x0))
+
+
+def test_anneal_schedule_split_matches_whole_run():
+    """Sweeps [0, 11) then [11, 25) of one 25-sweep schedule, the second part
+    starting from the first part's final states, reach the whole run's final
+    states; the better of the two parts' best energies is the whole run's."""
+    terms = W.cfg_int3(seed=12, n=14)
+    c = oracle.canonicalize(terms)
+    whole = oracle.anneal(c, 40, 25, 3.0, 0.1, seed=4)
+    a = oracle.anneal(c, 40, 11, 3.0, 0.1, seed=4, schedule_sweeps=25)
+    b = oracle.anneal(c, 40, 14, 3.0, 0.1, seed=4, init_bits=a["final_bits"], first_sweep=11, schedule_sweeps=25)
+    np.testing.assert_array_equal(b["final_bits"], whole["final_bits"])
+    np.testing.assert_array_equal(np.minimum(a["best_e"], b["best_e"]), whole["best_e"])
+    np.testing.assert_array_equal(np.minimum(a["trace"][-1], b["trace"]), whole["trace"][11:])
+    with pytest.raises(ValueError):
+        oracle.anneal(c, 4, 10, 3.0, 0.1, seed=4, first_sweep=20, schedule_sweeps=25)
