@@ -565,7 +565,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   // blocked kernel width: one 16-replica group per CU wants every wave; many groups fewer waves
   auto blk_waves = [&](int64_t tiles) {
     if (P.waves_per_block) return (int)P.waves_per_block;
-    return tiles <= 512 ? 4 : (tiles <= 2048 ? 2 : 1);
+    return tiles <= 384 ? 8 : (tiles <= 2048 ? 4 : 2);
   };
 
   // cache lookup

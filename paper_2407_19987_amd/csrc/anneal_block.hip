@@ -35,22 +35,23 @@ namespace hobo {
 
 constexpr int kRing = 8;       // chunks in flight per wave
 constexpr int kMaskWin = 64;   // sweeps per launch when attempt masks are used
+constexpr int kSweepWin = 256; // sweeps per launch otherwise (their trace waits in LDS)
 
 template <int P> struct BSlot {
   BTile<P> b;
   unsigned long long d;  // run descriptor of this lane's K group
   int kind;              // 0 chunk, 1 chunk closing its list, 2 padding, 3 end of stream
   int tgt;               // list of the chunk: 0 fields, 1 + t pair tile t
-  int blk_end;           // last slot of a block's sequence
+  int ord;               // active-block ordinal of the slot
 };
 
-struct BProd {           // producer cursor (wave-uniform)
-  int s, q;              // sweep and block being emitted
-  int li, nl;            // current list ordinal, lists of this wave in the block
-  unsigned c, stride;    // next chunk of the current list and its stride
-  int left, tgt;         // chunks left in the current list, its target
-  int pos, padded;       // slots emitted for the block, its padded length
-  int cnt_g;             // field chunks of this wave in the block
+template <int HT> struct BProd {  // producer cursor (wave-uniform, scalar registers)
+  int ord, s, q;         // active-block ordinal, its sweep and block
+  int k, padded;         // next slot of the block, the block's padded slot count
+  int cnt_g;             // field chunks of this wave (chunk g0 + k * NW)
+  unsigned g0;
+  int hs[HT], hn[HT];    // pair-tile m of this wave: slots hs .. hs + hn - 1 after the field chunks
+  unsigned hc0[HT];      // its first chunk
 };
 
 template <int CTRL> __device__ inline int dpp_i(int v) {
@@ -66,11 +67,24 @@ __device__ inline int quad_bcast(int v, int o) {
   }
 }
 
+// Eight-monomial mask of a run with at most one prefix variable (all runs of
+// an order <= 3 instance's block lists): the run's byte of the replica's bits,
+// cleared when the prefix bit is 0; constant and padding runs give 1 and 0.
+__device__ inline unsigned run_mask1(unsigned long long d, const unsigned char* rb) {
+  const unsigned np = (unsigned)(d >> 8) & 0xFFu;
+  const unsigned pv = (unsigned)(d >> 16) & 0xFFu;
+  const unsigned m = rb[(unsigned)d & 0x1Fu];
+  const unsigned pb = (rb[pv >> 3] >> (pv & 7u)) & 1u;
+  const unsigned v = (np == 1u && !pb) ? 0u : m;
+  return np == kRunConst ? 1u : (np == kRunNull ? 0u : v);
+}
+
 template <int P, int NW>
 __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
   constexpr int D = kRing;
   constexpr int RPC = PT<P>::RPC;
   constexpr int TB = P == P_FP32 ? 2048 : (P == P_BF16X2 ? 2048 : 3072);
+  constexpr int HT = (kPairTiles + NW - 1) / NW;  // pair tiles per wave
   __shared__ Luts L;
   __shared__ unsigned long long sbits[64];  // 16 replicas x 32 bytes
   __shared__ unsigned long long sbest[64];
@@ -80,9 +94,13 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
   __shared__ double sL[2][16][17];          // -log(u) [rep][bit]
   __shared__ BlockMeta sBM[kMaxVars / kBlockBits];
   __shared__ unsigned short sAM[kMaskWin][kMaxVars / kBlockBits];  // attempted bits per (sweep, block)
+  __shared__ unsigned short sAL[kMaskWin * (kMaxVars / kBlockBits)];  // active (sweep, block), stream order
+  __shared__ int sNA;                                                  // their number
+  __shared__ double strace[kSweepWin];  // per-sweep tile minima, written back after the launch's sweeps
 
   build_luts(&L);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave index, uniform
   const int g = lane >> 4, j = lane & 15;
   // phase-2 layout
   const int rep = lane >> 2, sub = lane & 3;
@@ -115,26 +133,42 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
     __syncthreads();
 
     auto block_bits = [&](int s, int q) -> unsigned {
-      const unsigned nb = sBM[q].nbits;
+      const unsigned nb = __builtin_amdgcn_readfirstlane(sBM[q].nbits);
       const unsigned full = (1u << nb) - 1u;
-      return masked ? (unsigned)sAM[s - p.s_begin][q] & full : full;
+      return masked ? __builtin_amdgcn_readfirstlane((unsigned)sAM[s - p.s_begin][q]) & full : full;
     };
-    // next active block after (s, q) in stream order; s == s_end when none
-    auto next_active = [&](int& s, int& q) {
-      do {
-        if (++q == NB) {
-          q = 0;
-          ++s;
+    // the active blocks of the launch, in stream order: every (sweep, block)
+    // without masks; with masks the list of those with an attempted bit
+    if (masked) {
+      if (w == 0) {
+        const int tot = (p.s_end - p.s_begin) * NB;
+        int cnt = 0;
+        for (int b0 = 0; b0 < tot; b0 += 64) {
+          const int e = b0 + lane;
+          const int sr = e / (NB > 0 ? NB : 1), q = e - sr * NB;
+          const bool act = e < tot && ((unsigned)sAM[sr][q] & ((1u << sBM[q].nbits) - 1u)) != 0u;
+          const unsigned long long bal = __builtin_amdgcn_ballot_w64(act);
+          const int pos = cnt + (int)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
+          if (act) sAL[pos] = (unsigned short)((sr << 4) | q);
+          cnt += (int)__builtin_popcountll(bal);
         }
-      } while (s < p.s_end && block_bits(s, q) == 0u);
-    };
-    auto first_active = [&](int& s, int& q) {
-      s = p.s_begin;
-      q = 0;
-      if (s < p.s_end && NB > 0 && block_bits(s, q) == 0u) next_active(s, q);
+        if (lane == 0) sNA = cnt;
+      }
+      __syncthreads();
+    }
+    const int nact = masked ? __builtin_amdgcn_readfirstlane(sNA) : (p.s_end - p.s_begin) * NB;
+    // (sweep, block) of active ordinal o, given those of o - 1
+    auto step_block = [&](int o, int& s, int& q) {
+      if (masked) {
+        const int v = __builtin_amdgcn_readfirstlane((int)sAL[o]);
+        s = p.s_begin + (v >> 4);
+        q = v & 15;
+      } else if (++q == NB) {
+        q = 0;
+        ++s;
+      }
     };
 
-    // ---- stage the triple table and -log(u) of block (s, q) into buffer bf
     auto stage_block = [&](int s, int q, int bf, int tid, int nthr, bool do_u) {
       const u4* src = reinterpret_cast<const u4*>(I.triples + (size_t)q * 4096);
       u4* dst = reinterpret_cast<u4*>(sC[bf]);
@@ -161,83 +195,77 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
       bestE = p.cont ? gld(I.best_track + myrow) : E;
     }
 
-    // ---- producer
-    BProd pr{};
-    auto setup_lists = [&]() {
+    // ---- producer: straight-line, scalar; block changes every `padded` slots
+    BProd<HT> pr{};
+    auto setup_block = [&]() {
       const BlockMeta& m = sBM[pr.q];
-      const int ng = (int)m.nchunks[0];
+      const int ng = __builtin_amdgcn_readfirstlane((int)m.nchunks[0]);
+      const int npt = __builtin_amdgcn_readfirstlane((int)m.npt);
       pr.cnt_g = ng > w ? (ng - w + NW - 1) / NW : 0;
-      int total = pr.cnt_g, nl = 1;
-      for (int t = w; t < (int)m.npt; t += NW) {
-        total += (int)m.nchunks[1 + t];
-        ++nl;
+      pr.g0 = __builtin_amdgcn_readfirstlane(m.chunk0[0]) + (unsigned)w;
+      int tot = 0;
+#pragma unroll
+      for (int mm = 0; mm < HT; ++mm) {
+        const int t = w + mm * NW;
+        const bool ok = t < npt;
+        pr.hs[mm] = tot;
+        pr.hn[mm] = ok ? __builtin_amdgcn_readfirstlane((int)m.nchunks[1 + (ok ? t : 0)]) : 0;
+        pr.hc0[mm] = ok ? __builtin_amdgcn_readfirstlane(m.chunk0[1 + (ok ? t : 0)]) : 0u;
+        tot += pr.hn[mm];
       }
-      pr.nl = nl;
-      pr.padded = total <= D ? D : (total + D - 1) / D * D;
-      pr.li = -1;
-      pr.left = 0;
-      pr.pos = 0;
-    };
-    auto open_list = [&]() {
-      const BlockMeta& m = sBM[pr.q];
-      if (pr.li == 0) {
-        pr.c = m.chunk0[0] + (unsigned)w;
-        pr.stride = NW;
-        pr.left = pr.cnt_g;
-        pr.tgt = 0;
-      } else {
-        const int t = w + (pr.li - 1) * NW;
-        pr.c = m.chunk0[1 + t];
-        pr.stride = 1;
-        pr.left = (int)m.nchunks[1 + t];
-        pr.tgt = 1 + t;
-      }
+      tot += pr.cnt_g;
+      pr.padded = tot <= D ? D : (tot + D - 1) / D * D;
+      pr.k = 0;
     };
     auto issue = [&](BSlot<P>& sl) {
-      unsigned c = 0, tix = 0;
-      int kind = 3, tgt = 0, be = 0;
-      for (;;) {
-        if (pr.s >= p.s_end) break;
-        if (pr.left > 0) {
-          c = pr.c;
-          tix = c + 1;
-          kind = pr.left == 1 ? 1 : 0;
-          tgt = pr.tgt;
-          be = pr.pos + 1 == pr.padded;
-          pr.c += pr.stride;
-          --pr.left;
-          ++pr.pos;
-          break;
+      if (pr.k == pr.padded) {  // the next active block
+        ++pr.ord;
+        if (pr.ord < nact) {
+          step_block(pr.ord, pr.s, pr.q);
+          setup_block();
         }
-        if (pr.li + 1 < pr.nl) {
-          ++pr.li;
-          open_list();
-          continue;
-        }
-        if (pr.pos < pr.padded) {
-          kind = 2;
-          be = pr.pos + 1 == pr.padded;
-          ++pr.pos;
-          break;
-        }
-        next_active(pr.s, pr.q);
-        if (pr.s < p.s_end) setup_lists();
+        pr.k = 0;
       }
-      sl.kind = kind;
-      sl.tgt = tgt;
-      sl.blk_end = be;
+      const int k = pr.k;
+      unsigned c = 0;
+      int kind = 2, tgt = 0;
+      if (k < pr.cnt_g) {
+        c = pr.g0 + (unsigned)(k * NW);
+        kind = k == pr.cnt_g - 1 ? 1 : 0;
+      } else {
+        const int kk = k - pr.cnt_g;
+#pragma unroll
+        for (int mm = 0; mm < HT; ++mm)
+          if (kk >= pr.hs[mm] && kk < pr.hs[mm] + pr.hn[mm]) {
+            c = pr.hc0[mm] + (unsigned)(kk - pr.hs[mm]);
+            kind = kk == pr.hs[mm] + pr.hn[mm] - 1 ? 1 : 0;
+            tgt = 1 + w + mm * NW;
+          }
+      }
+      pr.k = k + 1;
+      if (pr.ord >= nact) {  // past the last block
+        kind = 3;
+        c = 0;
+      }
+      sl.kind = __builtin_amdgcn_readfirstlane(kind);
+      sl.tgt = __builtin_amdgcn_readfirstlane(tgt);
+      sl.ord = __builtin_amdgcn_readfirstlane(pr.ord);
+      unsigned tix = kind <= 1 ? c + 1u : 0u;
       tix = tix < I.n_tiles ? tix : 0u;  // never outside the tile buffer
       load_tile<P>(sl.b, I.tiles + (size_t)tix * TB, lane);
       sl.d = gld(I.runs + (size_t)c * RPC + g);
     };
 
-    first_active(pr.s, pr.q);
-    if (pr.s < p.s_end) setup_lists();
-    int cs = pr.s, cq = pr.q;  // consumer block
-    int bf = 0;                // buffer of the consumer block's table and uniforms
-    if (cs < p.s_end) {
-      stage_block(cs, cq, 0, threadIdx.x, blockDim.x, true);
+    pr.ord = 0;
+    pr.s = p.s_begin;
+    pr.q = 0;
+    if (nact > 0) {
+      if (masked) step_block(0, pr.s, pr.q);
+      setup_block();
     }
+    int co = 0, cs = pr.s, cq = pr.q;  // consumer: active ordinal, sweep, block
+    int bf = 0;                        // buffer of the consumer block's table and uniforms
+    if (co < nact) stage_block(cs, cq, 0, threadIdx.x, blockDim.x, true);
     BSlot<P> ring[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) issue(ring[d]);
@@ -256,11 +284,12 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
         }
         double v = live ? bestE : INFINITY;
         for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-        if (I.trace_part && lane == 0) I.trace_part[(size_t)item.tile16 * p.sweeps + (s - p.s_first)] = v;
+        // kept in LDS: a global store here would make the stream's counted waits imprecise
+        if (lane == 0) strace[s - p.s_begin] = v;
       }
     };
 
-    while (cs < p.s_end) {
+    while (co < nact) {
       while (s_prev < cs) end_sweep(s_prev++);
       const int q = cq;
       const unsigned amask = block_bits(cs, q);
@@ -269,17 +298,21 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
       for (int e = lane; e < 256; e += 64) sG[w][e >> 4][e & 15] = 0.0f;
       for (int t = w; t < (int)bmq.npt; t += NW)
         for (int e = lane; e < 256; e += 64) sH[16 * t + (e & 15)][e >> 4] = 0.0f;
-      for (;;) {
-        int fin = 0;
+      // whole rounds of D slots belong to one block (its slot count is padded)
+      while (ring[0].ord == co) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           BSlot<P>& sl = ring[d];
-          if (sl.kind <= 1) {
+          {
+            // every slot's registers are consumed on every path (padding
+            // slots multiply a zero operand), so the counted waits stay exact
+            const unsigned m1 = run_mask1(sl.d, rb);
+            const unsigned msk = sl.kind <= 1 ? m1 : 0u;
             AOp<P> a;
             if constexpr (P == P_FP32) {
-              a.v = u4{run_mask(sl.d, rb), 0u, 0u, 0u};
+              a.v = u4{msk, 0u, 0u, 0u};
             } else {
-              a.v = L.bf16[run_mask(sl.d, rb)];
+              a.v = L.bf16[msk];
             }
             mma<P>(acc, a, sl.b);
             if (sl.kind == 1) {
@@ -293,15 +326,13 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
               acc_zero<P>(acc);
             }
           }
-          fin = sl.blk_end;
           issue(sl);
         }
-        if (fin) break;
       }
       lds_barrier();
       // ---- the next active block, for the staging wave
       int ns = cs, nq = cq;
-      next_active(ns, nq);
+      if (co + 1 < nact) step_block(co + 1, ns, nq);
       if (w == 0) {
         // ---- phase 2: sixteen sequential decisions
         const double beta = gld(p.beta + (cs - p.s_first));
@@ -362,13 +393,18 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
           myb[0] = (unsigned char)(xb & 0xFFu);
           myb[1] = (unsigned char)(xb >> 8);
         }
-        if (NW == 1 && ns < p.s_end) stage_block(ns, nq, bf ^ 1, lane, 64, true);
-      } else if (ns < p.s_end) {
+        if (NW == 1 && co + 1 < nact) stage_block(ns, nq, bf ^ 1, lane, 64, true);
+      } else if (co + 1 < nact) {
         // the other waves stage the next block's triple table and uniforms
         stage_block(ns, nq, bf ^ 1, threadIdx.x - 64, 64 * (NW - 1), true);
       }
+      // every load issued so far has landed (the ring's were issued before
+      // phase 2): the stream loop then starts from a known count of
+      // outstanding loads and keeps its ring in flight
+      __builtin_amdgcn_s_waitcnt(0x0F70);
       lds_barrier();
       bf ^= 1;
+      ++co;
       cs = ns;
       cq = nq;
     }
@@ -376,6 +412,9 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
 
     // write back (wave 0)
     if (w == 0) {
+      if (I.trace_part)
+        for (int s = p.s_begin + lane; s < p.s_end; s += 64)
+          I.trace_part[(size_t)item.tile16 * p.sweeps + (s - p.s_first)] = strace[s - p.s_begin];
       const int rho = lane >> 2, qw = lane & 3;
       const long long r = r0 + rho;
       if (qw < I.W && r < I.B) {
@@ -410,5 +449,6 @@ int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipS
 }
 
 int anneal_mask_window() { return kMaskWin; }
+int anneal_sweep_window() { return kSweepWin; }
 
 }  // namespace hobo

@@ -410,6 +410,7 @@ void anneal_shape(int T, int cs_req, int* ctw, int* cs) {
 
 int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipStream_t st);
 int anneal_mask_window();
+int anneal_sweep_window();
 
 // The annealing sequence of one launch plan, in three parts: random start
 // states and start energies (FP64 / int64 term sums); the sweeps (blocked
@@ -453,7 +454,7 @@ int enqueue_anneal_sweeps(const AnnealTables& tb, const AnnealPlan& pl, int s_be
     ap.items = tb.d_items + pl.item0;
     ap.n_items = pl.n_blk;
     const int nblk = pl.n_blk < 2048 ? pl.n_blk : 2048;
-    const int win = pl.masked ? anneal_mask_window() : (s_end > s_begin ? s_end - s_begin : 1);
+    const int win = pl.masked ? anneal_mask_window() : anneal_sweep_window();
     int s0 = s_begin;
     do {  // at least one launch: with no sweeps it writes the start states back as the best ones
       ap.s_begin = s0;
