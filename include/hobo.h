@@ -278,6 +278,19 @@ hobo_status hobo_mlp_train(float* state, const float* feats, const float* labels
 hobo_status hobo_proposal_features(const hobo_tensor* t, const uint64_t* x_bits, const uint64_t* x_after, int64_t B,
                                    const void* de, double beta, float* feats_out, float* labels_out, void* stream);
 
+/* ------------------------------------------------------------- autotuning */
+/* Times every launch shape of the kernels in fn_mask (1 energy: 16*rt
+ * replicas x 16*ct columns per wave; 2 fields: same; 4 annealing: waves per
+ * 16-replica work-group) for this tensor, precision and batch size on the
+ * caller's stream, with x_bits (device [W][B]) as input, and keeps the
+ * fastest for later calls with the same kernel, precision and
+ * ceil(log2 B).  Results never depend on the shape; only the time does.
+ * Blocks the host; not allowed under stream capture.  B <= 2^24.
+ * shapes_out: optional host int32[3], the chosen shapes (rt*16+ct, rt*16+ct,
+ * waves; 0 = not tuned). */
+hobo_status hobo_autotune(hobo_tensor* t, const uint64_t* x_bits, int64_t B, int32_t fn_mask, int32_t precision,
+                          int32_t* shapes_out, void* stream);
+
 /* ------------------------------------------------------------- timing */
 /* Kernel timing for measurement tools.  While enabled, each launch of the
  * annealing kernel (id 0), the fields kernel (id 1) and the energy kernel

@@ -47,22 +47,41 @@ bool valid_prec(int p) { return p >= HOBO_PREC_FP32 && p <= HOBO_PREC_FP64; }
 
 // Tile shape of the evaluation kernels: 16*rt replicas x 16*ct columns per
 // wave.  Narrower column groups give more waves when B is small.
-void eval_shape(const hobo::Tensor& t, int prec, int64_t B, int* rt, int* ct) {
+int tuned_shape(const hobo::Tensor& t, int kernel, int prec, int64_t B) {
+  std::lock_guard<std::mutex> lock(const_cast<hobo::Tensor&>(t).mu);
+  auto it = t.tuned.find(hobo::tune_key(kernel, prec, B));
+  return it == t.tuned.end() ? 0 : it->second;
+}
+
+void eval_shape(const hobo::Tensor& t, int prec, int64_t B, int* rt, int* ct, int kernel = 0) {
+  if (kernel) {
+    if (int sh = tuned_shape(t, kernel, prec, B)) {
+      *rt = sh >> 4;
+      *ct = sh & 15;
+      return;
+    }
+  }
   int T = (t.n_vars + 15) / 16;
   int c = 1;
   while (c < T && c < 8) c *= 2;
   if (prec == HOBO_PREC_INT8X4 && c > 4) c = 4;
   auto waves = [&](int cc, int rr) { return ((B + 16 * rr - 1) / (16 * rr)) * ((T + cc - 1) / cc); };
   while (c > 1 && waves(c, 1) < 1024) c /= 2;
-  int r = waves(c, 2) >= 2048 ? 2 : 1;
+  int r = waves(c, 4) >= 2048 ? 4 : (waves(c, 2) >= 2048 ? 2 : 1);
+  if (r == 4 && c > 4) c = 4;
   const char* env_rt = std::getenv("HOBO_EVAL_RT");
   const char* env_ct = std::getenv("HOBO_EVAL_CT");
-  if (env_rt) r = std::max(1, std::min(2, std::atoi(env_rt)));
+  if (env_rt) {
+    int v = std::atoi(env_rt);
+    r = v >= 4 ? 4 : (v >= 2 ? 2 : 1);
+  }
+  if (r == 4 && c > 4) c = 4;
   if (env_ct) {
     int v = std::atoi(env_ct);
     c = v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 1;
     if (prec == HOBO_PREC_INT8X4 && c > 4) c = 4;
   }
+  if (r == 4 && c > 4) c = 4;  // instantiated shapes: rt 4 with up to 4 column tiles
   *rt = r;
   *ct = c;
 }
@@ -380,7 +399,7 @@ hobo_status hobo_energy(const hobo_tensor* tc, const uint64_t* x_bits, int64_t B
   hobo::Packed* pk;
   if (int s = hobo::get_packed(&t->t, hobo::M_ENERGY, precision, &pk, &err)) return fail(s, err);
   int rt, ct;
-  eval_shape(t->t, precision, B, &rt, &ct);
+  eval_shape(t->t, precision, B, &rt, &ct, hobo::TK_ENERGY);
   size_t wb = hobo::eval_workspace_bytes(&t->t, hobo::M_ENERGY, B, ct);
   void* work = nullptr;
   if (wb) {
@@ -414,7 +433,7 @@ hobo_status hobo_local_fields(const hobo_tensor* tc, const uint64_t* x_bits, int
   hobo::Packed* pk;
   if (int s = hobo::get_packed(&t->t, hobo::M_FIELDS, precision, &pk, &err)) return fail(s, err);
   int rt, ct;
-  eval_shape(t->t, precision, B, &rt, &ct);
+  eval_shape(t->t, precision, B, &rt, &ct, hobo::TK_FIELDS);
   size_t wb = e_out ? hobo::eval_workspace_bytes(&t->t, hobo::M_FIELDS, B, ct) : 0;
   void* work = nullptr;
   if (wb) {
@@ -551,6 +570,10 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     beta[(size_t)s] = 1.0 / T;
   }
   const int init_random = P.init == HOBO_INIT_RANDOM ? 1 : 0;
+  // waves per work-group of the per-bit slab kernel: requested, tuned, or its default
+  const int slab_waves = P.waves_per_block ? P.waves_per_block
+                         : (n_instances == 1 ? tuned_shape(tensors[0]->t, hobo::TK_ANNEAL, P.precision, replicas[0])
+                                             : 0);
   auto base_plan = [&]() {
     hobo::AnnealPlan pl;
     pl.sweeps = S;
@@ -565,6 +588,8 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   // blocked kernel width: one 16-replica group per CU wants every wave; many groups fewer waves
   auto blk_waves = [&](int64_t tiles) {
     if (P.waves_per_block) return (int)P.waves_per_block;
+    if (n_instances == 1)
+      if (int sh = tuned_shape(tensors[0]->t, hobo::TK_ANNEAL, P.precision, replicas[0])) return sh;
     return tiles <= 384 ? 8 : (tiles <= 2048 ? 4 : 2);
   };
 
@@ -664,7 +689,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
         learn_off += align((size_t)nt * P.refresh * T.n_vars);
         L.x = x_inout + xoff;
         L.B = Bj;
-        eval_shape(T, P.precision, Bj, &L.rt, &L.ct);
+        eval_shape(T, P.precision, Bj, &L.rt, &L.ct, hobo::TK_FIELDS);
         d.attempt = L.mask;
         ne.learn.push_back(L);
       }
@@ -702,7 +727,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       att_off += (int64_t)nt * S * T.n_vars;
       if (!blocked[(size_t)j]) {
         int ctj, nwj;
-        hobo::anneal_shape((T.n_vars + 15) / 16, P.waves_per_block, &ctj, &nwj);
+        hobo::anneal_shape((T.n_vars + 15) / 16, slab_waves, &ctj, &nwj);
         max_ct = std::max(max_ct, ctj);
         max_nw = std::max(max_nw, nwj);
       }
@@ -723,7 +748,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
           pl.nw_blk = blk_waves(nt);
         } else {
           pl.n_slab = nt;
-          hobo::anneal_shape((tensors[j]->t.n_vars + 15) / 16, P.waves_per_block, &pl.ct, &pl.nw);
+          hobo::anneal_shape((tensors[j]->t.n_vars + 15) / 16, slab_waves, &pl.ct, &pl.nw);
         }
         items.insert(items.end(), items_of[(size_t)j].begin(), items_of[(size_t)j].end());
         ne.plans.push_back(pl);
@@ -746,7 +771,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       int maxT = 1;
       for (int j = 0; j < n_instances; ++j)
         if (!blocked[(size_t)j]) maxT = std::max(maxT, (tensors[j]->t.n_vars + 15) / 16);
-      hobo::anneal_shape(maxT, P.waves_per_block, &pl.ct, &pl.nw);
+      hobo::anneal_shape(maxT, slab_waves, &pl.ct, &pl.nw);
       ne.plans.push_back(pl);
     }
     (void)max_ct;
@@ -890,6 +915,122 @@ hobo_status hobo_proposal_features(const hobo_tensor* tc, const uint64_t* x_bits
                                       t->t.integer ? 1 : 0, beta, rn, feats_out, labels_out, (hipStream_t)stream,
                                       &err))
     return fail(s, err);
+  return ok();
+}
+
+// ------------------------------------------------------------ autotuning
+hobo_status hobo_autotune(hobo_tensor* t, const uint64_t* x_bits, int64_t B, int32_t fn_mask, int32_t precision,
+                          int32_t* shapes_out, void* stream) {
+  g_err.clear();
+  if (hobo_status s = check_bits_args(t, x_bits, B, precision)) return s;
+  if (fn_mask < 1 || fn_mask > 7) return fail(HOBO_ERR_INVALID_ARG, "fn_mask must combine 1, 2 and 4");
+  if (precision == HOBO_PREC_FP64) return fail(HOBO_ERR_PRECISION, "FP64 has no tiled kernels to tune");
+  if (B > ((int64_t)1 << 24)) return fail(HOBO_ERR_INVALID_ARG, "tune with at most 2^24 states");
+  if (hobo_status s = need_device()) return s;
+  hipStream_t st = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(HOBO_ERR_INVALID_ARG, "hobo_autotune blocks the host; it cannot run under stream capture");
+  const hobo::Tensor& T = t->t;
+  const int n = T.n_vars, W = (n + 63) / 64;
+  std::string err;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  void *e = nullptr, *de = nullptr, *xa = nullptr, *bx = nullptr, *be = nullptr;
+  int rc = HOBO_OK;
+  auto H = [&](hipError_t x, const char* what) {
+    if (rc == HOBO_OK && x != hipSuccess) rc = hip_status(x, what);
+    return rc == HOBO_OK;
+  };
+  // time one candidate: a warm-up call, then the best of three timed calls
+  auto time_it = [&](auto&& call) -> float {
+    float best = 1e30f;
+    if (call() != HOBO_OK) return -1.0f;
+    for (int r = 0; r < 3 && rc == HOBO_OK; ++r) {
+      if (!H(hipEventRecord(ev0, st), "hipEventRecord")) break;
+      if (call() != HOBO_OK) return -1.0f;
+      if (!H(hipEventRecord(ev1, st), "hipEventRecord") || !H(hipEventSynchronize(ev1), "hipEventSynchronize")) break;
+      float ms = 0.0f;
+      if (!H(hipEventElapsedTime(&ms, ev0, ev1), "hipEventElapsedTime")) break;
+      best = std::min(best, ms);
+    }
+    return rc == HOBO_OK ? best : -1.0f;
+  };
+  int chosen[3] = {0, 0, 0};
+  if (H(hipEventCreate(&ev0), "hipEventCreate") && H(hipEventCreate(&ev1), "hipEventCreate") &&
+      H(hipMalloc(&e, (size_t)B * 8), "hipMalloc") && H(hipMalloc(&de, (size_t)B * n * 8), "hipMalloc")) {
+    for (int f = 0; f < 2 && rc == HOBO_OK; ++f) {
+      const int kernel = f == 0 ? hobo::TK_ENERGY : hobo::TK_FIELDS;
+      if (!(fn_mask & (f == 0 ? 1 : 2))) continue;
+      float best = 1e30f;
+      int pick = 0;
+      for (int rt = 1; rt <= 4 && rc == HOBO_OK; rt *= 2)
+        for (int ct = 1; ct <= 8 && rc == HOBO_OK; ct *= 2) {
+          if ((precision == HOBO_PREC_INT8X4 || rt == 4) && ct > 4) continue;
+          {
+            std::lock_guard<std::mutex> lock(t->t.mu);
+            t->t.tuned[hobo::tune_key(kernel, precision, B)] = rt * 16 + ct;
+          }
+          float ms = time_it([&]() -> int {
+            hobo_status s = f == 0 ? hobo_energy(t, x_bits, B, precision, e, stream)
+                                   : hobo_local_fields(t, x_bits, B, precision, de, nullptr, stream);
+            if (s != HOBO_OK && rc == HOBO_OK) rc = s;
+            return s;
+          });
+          if (ms >= 0.0f && ms < best) {
+            best = ms;
+            pick = rt * 16 + ct;
+          }
+        }
+      std::lock_guard<std::mutex> lock(t->t.mu);
+      if (pick) t->t.tuned[hobo::tune_key(kernel, precision, B)] = pick;
+      else t->t.tuned.erase(hobo::tune_key(kernel, precision, B));
+      chosen[f] = pick;
+    }
+    if ((fn_mask & 4) && rc == HOBO_OK && H(hipMalloc(&xa, (size_t)W * B * 8), "hipMalloc") &&
+        H(hipMalloc(&bx, (size_t)W * B * 8), "hipMalloc") && H(hipMalloc(&be, (size_t)B * 8), "hipMalloc")) {
+      float best = 1e30f;
+      int pick = 0;
+      const int cand[4] = {1, 2, 4, 8};
+      for (int q = 0; q < 4 && rc == HOBO_OK; ++q) {
+        hobo_anneal_params ap{};
+        ap.sweeps = 8;
+        ap.precision = precision;
+        ap.t_start = 2.0;
+        ap.t_end = 1.0;
+        ap.seed = 1;
+        ap.init = HOBO_INIT_GIVEN;
+        ap.waves_per_block = cand[q];
+        hobo_tensor* ts[1] = {t};
+        const int64_t reps[1] = {B};
+        float ms = time_it([&]() -> int {
+          if (!H(hipMemcpyAsync(xa, x_bits, (size_t)W * B * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync"))
+            return rc;
+          hobo_status s = hobo_anneal_batch(ts, 1, reps, &ap, static_cast<uint64_t*>(xa), static_cast<uint64_t*>(bx),
+                                            be, nullptr, HOBO_LAUNCH_PERSISTENT, stream);
+          if (s != HOBO_OK && rc == HOBO_OK) rc = s;
+          return s;
+        });
+        if (ms >= 0.0f && ms < best) {
+          best = ms;
+          pick = cand[q];
+        }
+      }
+      std::lock_guard<std::mutex> lock(t->t.mu);
+      if (pick) t->t.tuned[hobo::tune_key(hobo::TK_ANNEAL, precision, B)] = pick;
+      chosen[2] = pick;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  if (e) (void)hipFree(e);
+  if (de) (void)hipFree(de);
+  if (xa) (void)hipFree(xa);
+  if (bx) (void)hipFree(bx);
+  if (be) (void)hipFree(be);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (rc != HOBO_OK) return rc;
+  if (shapes_out)
+    for (int k = 0; k < 3; ++k) shapes_out[k] = chosen[k];
   return ok();
 }
 

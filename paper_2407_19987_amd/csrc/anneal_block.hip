@@ -217,8 +217,10 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
       pr.padded = tot <= D ? D : (tot + D - 1) / D * D;
       pr.k = 0;
     };
-    auto issue = [&](BSlot<P>& sl) {
-      if (pr.k == pr.padded) {  // the next active block
+    // the producer enters its next active block; its slot counts are whole
+    // rounds of D, so this happens only between rounds
+    auto advance = [&]() {
+      if (pr.k == pr.padded) {
         ++pr.ord;
         if (pr.ord < nact) {
           step_block(pr.ord, pr.s, pr.q);
@@ -226,6 +228,8 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
         }
         pr.k = 0;
       }
+    };
+    auto issue = [&](BSlot<P>& sl) {
       const int k = pr.k;
       unsigned c = 0;
       int kind = 2, tgt = 0;
@@ -300,31 +304,38 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
         for (int e = lane; e < 256; e += 64) sH[16 * t + (e & 15)][e >> 4] = 0.0f;
       // whole rounds of D slots belong to one block (its slot count is padded)
       while (ring[0].ord == co) {
+        advance();
+        // one round: the operand of slot d + 1 is generated before the
+        // matrix-core work of slot d, so its LDS reads overlap that work
+        auto gen = [&](const BSlot<P>& sl) {
+          // every slot's registers are consumed on every path (padding slots
+          // multiply a zero operand), so the counted waits stay exact
+          const unsigned m1 = run_mask1(sl.d, rb);
+          const unsigned msk = sl.kind <= 1 ? m1 : 0u;
+          AOp<P> a;
+          if constexpr (P == P_FP32) {
+            a.v = u4{msk, 0u, 0u, 0u};
+          } else {
+            a.v = L.bf16[msk];
+          }
+          return a;
+        };
+        AOp<P> an = gen(ring[0]);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           BSlot<P>& sl = ring[d];
-          {
-            // every slot's registers are consumed on every path (padding
-            // slots multiply a zero operand), so the counted waits stay exact
-            const unsigned m1 = run_mask1(sl.d, rb);
-            const unsigned msk = sl.kind <= 1 ? m1 : 0u;
-            AOp<P> a;
-            if constexpr (P == P_FP32) {
-              a.v = u4{msk, 0u, 0u, 0u};
+          const AOp<P> a = an;
+          if (d + 1 < D) an = gen(ring[d + 1 < D ? d + 1 : 0]);
+          mma<P>(acc, a, sl.b);
+          if (sl.kind == 1) {  // the chunk closes its list: fields [rep][bit], pairs [pair][rep]
+            if (sl.tgt == 0) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) sG[w][4 * g + r][j] = acc.v[r];
             } else {
-              a.v = L.bf16[msk];
-            }
-            mma<P>(acc, a, sl.b);
-            if (sl.kind == 1) {
-              if (sl.tgt == 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sG[w][4 * g + r][j] = acc.v[r];
-              } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sH[16 * (sl.tgt - 1) + j][4 * g + r] = acc.v[r];
-              }
-              acc_zero<P>(acc);
+              for (int r = 0; r < 4; ++r) sH[16 * (sl.tgt - 1) + j][4 * g + r] = acc.v[r];
             }
+            acc_zero<P>(acc);
           }
           issue(sl);
         }

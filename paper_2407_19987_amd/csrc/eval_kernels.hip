@@ -34,8 +34,8 @@ struct EvalParams {
 // chunks in flight per wave in the evaluation kernels
 template <int P, int CT> constexpr int ring_depth_eval() {
   constexpr int per = CT * PT<P>::NLD * 4 + 4;
-  constexpr int d = 96 / per;
-  return d < 2 ? 2 : (d > 6 ? 6 : d);
+  constexpr int d = 160 / per;
+  return d < 2 ? 2 : (d > 8 ? 8 : d);
 }
 constexpr int kEvalMetaBlock = 1024;  // chunk metadata staged in LDS per block
 
@@ -70,10 +70,11 @@ __global__ __launch_bounds__(64 * NW) void eval_kernel(EvalParams p) {
   for (int rt = 0; rt < RT; ++rt)
     for (int t = 0; t < CT; ++t) acc_zero<P>(acc[rt][t]);
   // fields mode: per-order energy bookkeeping (Euler: sum_i x_i g_i^(r) = r E^(r))
-  double eacc[RT][4], prevd[RT][4];
-  long long eacci[RT][4], previ[RT][4];
+  // one 64-bit register pair per value: int64 for integer tensors, the bits
+  // of a double otherwise
+  long long eacc[RT][4], prevv[RT][4];
   for (int rt = 0; rt < RT; ++rt)
-    for (int r = 0; r < 4; ++r) { eacc[rt][r] = 0.0; prevd[rt][r] = 0.0; eacci[rt][r] = 0; previ[rt][r] = 0; }
+    for (int r = 0; r < 4; ++r) { eacc[rt][r] = 0; prevv[rt][r] = 0; }
 
   // coefficient stream: chunk c's tiles of this column group and run
   // descriptors, D chunks in flight; chunk metadata is fetched one ahead
@@ -169,8 +170,8 @@ __global__ __launch_bounds__(64 * NW) void eval_kernel(EvalParams p) {
               int col = 16 * (tbase + t) + j;
               if (col < p.n_vars && bit_at(rb, col)) d += acc_i<P>(acc[rt][t], r);
             }
-            eacci[rt][r] += (long long)(kLcm / ord) * (d - previ[rt][r]);
-            previ[rt][r] = d;
+            eacc[rt][r] += (long long)(kLcm / ord) * (d - prevv[rt][r]);
+            prevv[rt][r] = d;
           } else {
             double d = 0.0;
 #pragma unroll
@@ -178,8 +179,10 @@ __global__ __launch_bounds__(64 * NW) void eval_kernel(EvalParams p) {
               int col = 16 * (tbase + t) + j;
               if (col < p.n_vars && bit_at(rb, col)) d += acc_f<P>(acc[rt][t], r);
             }
-            eacc[rt][r] += (double)(kLcm / ord) * (d - prevd[rt][r]);
-            prevd[rt][r] = d;
+            const double e = __longlong_as_double(eacc[rt][r]) +
+                             (double)(kLcm / ord) * (d - __longlong_as_double(prevv[rt][r]));
+            eacc[rt][r] = __double_as_longlong(e);
+            prevv[rt][r] = __double_as_longlong(d);
           }
         }
     }
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(64 * NW) void eval_kernel(EvalParams p) {
         if (p.integer) {
           long long v;
           if (MODE == M_FIELDS) {
-            v = group_sum_i(eacci[rt][r]);
+            v = group_sum_i(eacc[rt][r]);
           } else {
             v = 0;
             for (int t = 0; t < CT; ++t) {
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(64 * NW) void eval_kernel(EvalParams p) {
         } else {
           double v;
           if (MODE == M_FIELDS) {
-            v = group_sum(eacc[rt][r]);
+            v = group_sum(__longlong_as_double(eacc[rt][r]));
           } else {
             // per 16-column tile sums added in column order: the result does
             // not depend on how tiles are grouped into waves
@@ -340,6 +343,7 @@ static int dispatch_eval_shape(const EvalParams& ep, int rt, int ct, long long B
   }
   HOBO_EV(1, 1) HOBO_EV(1, 2) HOBO_EV(1, 4) HOBO_EV(1, 8)
   HOBO_EV(2, 1) HOBO_EV(2, 2) HOBO_EV(2, 4) HOBO_EV(2, 8)
+  HOBO_EV(4, 1) HOBO_EV(4, 2) HOBO_EV(4, 4)
 #undef HOBO_EV
   return -1;
 }

@@ -135,9 +135,19 @@ struct Tensor {
   std::map<int, std::unique_ptr<Packed>> packed;  // key = mode*16 + prec
   std::unique_ptr<TermsDev> terms;
   double* d_row_norm = nullptr;  // device copy of row_norm (uploaded on first use)
+  // autotuned launch shapes (hobo_autotune): key = (kernel << 16) | (prec << 8) | ceil(log2 B)
+  std::map<uint32_t, int> tuned;
   ~Tensor();
   int n_mono() const { return (int)(mono_ptr.size() - 1); }
 };
+
+// kernels with tuned shapes
+enum TuneKernel : int { TK_FIELDS = 1, TK_ENERGY = 2, TK_ANNEAL = 3 };
+inline uint32_t tune_key(int kernel, int prec, int64_t B) {
+  int bc = 0;
+  while (bc < 62 && ((int64_t)1 << bc) < B) ++bc;
+  return ((uint32_t)kernel << 16) | ((uint32_t)prec << 8) | (uint32_t)bc;
+}
 
 // ------------------------------------------------------------------ status
 struct Error {

@@ -33,7 +33,7 @@ EXPORTS = [
     "hobo_build_tensor", "hobo_free_tensor", "hobo_tensor_info_get", "hobo_tensor_monomials",
     "hobo_tensor_export_dense", "hobo_tensor_prepare", "hobo_energy", "hobo_local_fields",
     "hobo_anneal_batch", "hobo_timing_enable", "hobo_timing_read", "hobo_last_error", "hobo_version",
-    "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features",
+    "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features", "hobo_autotune",
 ]
 
 
@@ -80,6 +80,7 @@ def _load():
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
     lib.hobo_mlp_forward.argtypes = [P, P, i64, P, P]
     lib.hobo_mlp_grad.argtypes = [P, P, P, i64, P, P, P]
+    lib.hobo_autotune.argtypes = [P, P, i64, i32, i32, P, P]
     lib.hobo_mlp_train.argtypes = [P, P, P, i64, ctypes.POINTER(MlpTrainParams), P, P]
     lib.hobo_proposal_features.argtypes = [P, P, P, i64, P, ctypes.c_double, P, P, P]
     lib.hobo_timing_enable.argtypes = [i32]
@@ -315,6 +316,15 @@ def proposal_features(t: Tensor, x_bits, B: int, de, beta: float, feats_out, x_a
     _check(lib.hobo_proposal_features(t.handle, _dev_ptr(x_bits), _dev_ptr(x_after) if x_after is not None else None,
                                       int(B), _dev_ptr(de), float(beta), _dev_ptr(feats_out),
                                       _dev_ptr(labels_out) if labels_out is not None else None, _stream(stream)))
+
+
+def autotune(t: Tensor, x_bits, B: int, fn_mask: int, precision: int, stream=None):
+    """hobo_autotune: returns the chosen shapes (energy, fields, anneal)."""
+    _check_bits(t, x_bits, B)
+    out = np.zeros(3, dtype=np.int32)
+    _check(lib.hobo_autotune(t.handle, _dev_ptr(x_bits), int(B), int(fn_mask), int(precision), _np_ptr(out),
+                             _stream(stream)))
+    return tuple(int(v) for v in out)
 
 
 KERNEL_ANNEAL, KERNEL_FIELDS, KERNEL_ENERGY = 0, 1, 2

@@ -76,7 +76,7 @@ def train(feats, labels, params0: np.ndarray, *, batch: int = 4096, epochs: int 
 
 def anneal_timed(t: "hobo.Tensor", replicas: int, sweeps: int, t_start: float, t_end: float, seed: int, *,
                  precision: int = hobo.PREC_BF16X2, mlp=None, tau: float = 0.5, p_floor: float = 0.0,
-                 refresh: int = 10, repeats: int = 1):
+                 refresh: int = 10, repeats: int = 1, algorithm: int = hobo.ANNEAL_AUTO):
     """One annealing call (LEARNED when ``mlp`` is given) timed with HIP
     events around the call on the current stream; returns dict(ms, best_e,
     trace) of the last repeat."""
@@ -88,7 +88,8 @@ def anneal_timed(t: "hobo.Tensor", replicas: int, sweeps: int, t_start: float, t
     bx = torch.zeros_like(x)
     be = torch.zeros(b, dtype=torch.int64 if t.integer else torch.float64, device="cuda")
     tr = torch.zeros(max(sweeps, 1), dtype=torch.float64, device="cuda")
-    kw = dict(sweeps=sweeps, t_start=t_start, t_end=t_end, seed=seed, precision=precision, trace_out=tr)
+    kw = dict(sweeps=sweeps, t_start=t_start, t_end=t_end, seed=seed, precision=precision, trace_out=tr,
+              algorithm=algorithm)
     if mlp is not None:
         kw.update(mlp=mlp, tau=tau, p_floor=p_floor, refresh=refresh)
     hobo.anneal_batch(t, b, x, bx, be, **kw)  # warm-up: layouts and cached setup
