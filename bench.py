@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-eval-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mixed-instances", type=int, default=16,
+                    help="instances of the mixed family for the persistent-vs-per-instance comparison (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (scale for the HBM traffic counters)")
     args = ap.parse_args()
@@ -224,6 +226,43 @@ def main():
                         us=us, evals_per_s=bb / (us * 1e-6), issued_tflops=tfl,
                         frac_of_peak=tfl / PEAK_TFLOPS[pname])
 
+    # many instances of uneven size and order in one persistent, graph-captured
+    # launch against one launch sequence per instance (same kernels and shapes)
+    multi = None
+    if args.mixed_instances > 0:
+        mi, mb, msw = args.mixed_instances, 256, 100
+        th0 = time.perf_counter()
+        mts = [hobo.Tensor.from_terms(W.cfg_mixed_instance(0, i)) for i in range(mi)]
+        for mt in mts:
+            mt.prepare(hobo.FN_ANNEAL, 1 << PREC_OF["fp32"])
+        host_s = time.perf_counter() - th0
+        words = sum(((mt.n_vars + 63) // 64) * mb for mt in mts)
+        mx = torch.zeros(words, dtype=torch.int64, device=dev)
+        mbx = torch.zeros_like(mx)
+        mbe = torch.zeros(mi * mb, dtype=torch.float64, device=dev)
+        mtr = torch.zeros(mi * msw, dtype=torch.float64, device=dev)
+        res = {}
+        for name, mode in (("per_instance", hobo.LAUNCH_PER_INSTANCE), ("persistent_graph", hobo.LAUNCH_GRAPH)):
+            kw = dict(sweeps=msw, t_start=T0, t_end=T1, seed=3, precision=PREC_OF["fp32"], trace_out=mtr,
+                      launch_mode=mode)
+            hobo.anneal_batch(mts, [mb] * mi, mx, mbx, mbe, **kw)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(2):
+                hobo.anneal_batch(mts, [mb] * mi, mx, mbx, mbe, **kw)
+            b.record()
+            torch.cuda.synchronize()
+            res[name] = dict(ms=a.elapsed_time(b) / 2, best=mbe.cpu().numpy().copy())
+        same = bool(np.array_equal(res["per_instance"]["best"], res["persistent_graph"]["best"]))
+        multi = {"instances": mi, "replicas_each": mb, "sweeps": msw, "precision": "fp32",
+                 "orders": [int(mt.order) for mt in mts], "n_vars": [int(mt.n_vars) for mt in mts],
+                 "per_instance_ms": res["per_instance"]["ms"], "persistent_graph_ms": res["persistent_graph"]["ms"],
+                 "speedup": res["per_instance"]["ms"] / res["persistent_graph"]["ms"],
+                 "replica_sweeps_per_s": mi * mb * msw / (res["persistent_graph"]["ms"] / 1e3),
+                 "identical_results": same, "host_build_pack_s": host_s,
+                 "sample": f"instances 0..{mi - 1} of the mixed family (master seed 0)"}
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -234,7 +273,7 @@ def main():
         t0 = time.perf_counter()
         oracle.anneal(c, nrep, nsw, T0, T1, seed=42)
         probe = time.perf_counter() - t0
-        nsw = int(max(10, min(S, nsw * 15.0 / max(probe, 1e-3))))
+        nsw = int(max(10, min(S, nsw * 20.0 / max(probe, 1e-3))))
         t0 = time.perf_counter()
         oracle.anneal(c, nrep, nsw, T0, T1, seed=42, schedule_sweeps=S)
         dt = time.perf_counter() - t0
@@ -242,6 +281,26 @@ def main():
                "sample": f"oracle annealer, {nrep} replicas x the first {nsw} sweeps of the same N=128 order-3 "
                          f"instance's {S}-sweep schedule (T {T0}->{T1}), {dt:.1f} s on "
                          f"{platform.processor() or platform.machine()}"}
+
+    # HBM traffic of the dominant kernel from the committed counter summary,
+    # valid only for the kernel source it was measured on
+    traffic = None
+    try:
+        import hashlib
+        import re
+
+        src = os.path.join(ROOT, "paper_2407_19987_amd", "csrc", "anneal_block.hip")
+        prof = os.path.join(ROOT, "profiles", "anneal_block_traffic_order3_n128_b4096.md")
+        txt = open(prof).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        row = re.search(r"`anneal_block_kernel<1, 8>` \(BF16x2\) \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|", txt)
+        fs = float(re.search(r"FETCH x ([0-9.]+)", txt).group(1))
+        ws = float(re.search(r"WRITE x ([0-9.]+)", txt).group(1))
+        if (digest in txt and row and args.precision == "bf16x2" and B == REPLICAS and S == SWEEPS
+                and main_res["anneal_launches"] == 4):
+            traffic = (float(row.group(1)) * fs + float(row.group(2)) * ws) * 1024.0
+    except (OSError, AttributeError, ValueError):
+        traffic = None
 
     rec = {
         "metric": "HOBO energy+ΔE evals/s; time-to-target energy, plain vs split/learned",
@@ -260,13 +319,14 @@ def main():
                                f"{S} Metropolis sweeps T {T0}->{T1}, energy + fields + anneal per step",
                    "n_vars": N_VARS, "order": ORDER, "replicas": B, "sweeps": S, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": "anneal_block_kernel",
+                     "traffic": traffic, "kernel": "anneal_block_kernel",
                      "flops_per_launch": flops // max(main_res["anneal_launches"], 1),
                      "avg_launch_ms": main_res["anneal_ms"] / max(main_res["anneal_launches"], 1),
                      "launches_per_step": main_res["anneal_launches"]},
         "variants": variants,
         "learned": learned_info,
         "eval_kernels": eval_info,
+        "multi_instance": multi,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
