@@ -175,8 +175,9 @@ typedef struct {
   int32_t proposal;    /* METROPOLIS, MASKED (attempt masks) or LEARNED (network) */
   const uint8_t* attempt; /* MASKED: device uint8 [ceil(B/16)][sweeps][N] per instance,
                              concatenated; 1 = the 16-replica group visits the bit */
-  int32_t waves_per_block; /* waves sharing 16 replicas (1, 2, 4, 8); 0 = default.
-                              Results do not depend on it. */
+  int32_t waves_per_block; /* waves sharing 16 replicas (1, 2, 4, 8, 16); 0 = default.
+                              The per-bit kernel uses at most 8, the blocked one at
+                              least 2.  Results do not depend on it. */
   int32_t algorithm;   /* HOBO_ANNEAL_AUTO | SLABS | BLOCKS */
   int32_t first_sweep; /* this call runs sweeps first_sweep .. first_sweep+sweeps-1 */
   int32_t schedule_sweeps; /* L, length of the whole schedule; 0 = sweeps (first_sweep

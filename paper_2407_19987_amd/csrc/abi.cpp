@@ -67,7 +67,11 @@ void eval_shape(const hobo::Tensor& t, int prec, int64_t B, int* rt, int* ct, in
   if (prec == HOBO_PREC_INT8X4 && c > 4) c = 4;
   auto waves = [&](int cc, int rr) { return ((B + 16 * rr - 1) / (16 * rr)) * ((T + cc - 1) / cc); };
   while (c > 1 && waves(c, 1) < 1024) c /= 2;
-  int r = waves(c, 4) >= 2048 ? 4 : (waves(c, 2) >= 2048 ? 2 : 1);
+  // The energy contraction gains from several row tiles per wave once the
+  // grid is full; the fields contraction keeps one per-bit accumulator per
+  // row tile and loses more to register pressure than it gains in reuse.
+  int r = 1;
+  if (kernel != hobo::TK_FIELDS) r = waves(c, 4) >= 2048 ? 4 : (waves(c, 2) >= 2048 ? 2 : 1);
   if (r == 4 && c > 4) c = 4;
   const char* env_rt = std::getenv("HOBO_EVAL_RT");
   const char* env_ct = std::getenv("HOBO_EVAL_CT");
@@ -480,8 +484,8 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   if (launch_mode < HOBO_LAUNCH_PER_INSTANCE || launch_mode > HOBO_LAUNCH_GRAPH)
     return fail(HOBO_ERR_INVALID_ARG, "unknown launch_mode");
   if (P.waves_per_block != 0 && P.waves_per_block != 1 && P.waves_per_block != 2 && P.waves_per_block != 4 &&
-      P.waves_per_block != 8)
-    return fail(HOBO_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
+      P.waves_per_block != 8 && P.waves_per_block != 16)
+    return fail(HOBO_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4, 8 or 16");
   if (P.algorithm < HOBO_ANNEAL_AUTO || P.algorithm > HOBO_ANNEAL_BLOCKS)
     return fail(HOBO_ERR_INVALID_ARG, "unknown algorithm");
   bool all_int = true, any_int = false;
@@ -571,9 +575,11 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   }
   const int init_random = P.init == HOBO_INIT_RANDOM ? 1 : 0;
   // waves per work-group of the per-bit slab kernel: requested, tuned, or its default
-  const int slab_waves = P.waves_per_block ? P.waves_per_block
-                         : (n_instances == 1 ? tuned_shape(tensors[0]->t, hobo::TK_ANNEAL, P.precision, replicas[0])
-                                             : 0);
+  // (at most 8: a request of 16 means the widest)
+  const int slab_waves = std::min(8, P.waves_per_block ? P.waves_per_block
+                                     : (n_instances == 1 ? tuned_shape(tensors[0]->t, hobo::TK_ANNEAL,
+                                                                       P.precision, replicas[0])
+                                                         : 0));
   auto base_plan = [&]() {
     hobo::AnnealPlan pl;
     pl.sweeps = S;
@@ -585,12 +591,14 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     pl.prec = P.precision;
     return pl;
   };
-  // blocked kernel width: one 16-replica group per CU wants every wave; many groups fewer waves
+  // blocked kernel width (one decision wave plus streaming waves, so at
+  // least 2): one 16-replica group per CU wants all sixteen waves, two
+  // groups per CU eight each
   auto blk_waves = [&](int64_t tiles) {
-    if (P.waves_per_block) return (int)P.waves_per_block;
-    if (n_instances == 1)
-      if (int sh = tuned_shape(tensors[0]->t, hobo::TK_ANNEAL, P.precision, replicas[0])) return sh;
-    return tiles <= 384 ? 8 : (tiles <= 2048 ? 4 : 2);
+    int nw = P.waves_per_block;
+    if (!nw && n_instances == 1) nw = tuned_shape(tensors[0]->t, hobo::TK_ANNEAL, P.precision, replicas[0]);
+    if (!nw) nw = tiles <= 256 ? 16 : 8;
+    return nw < 2 ? 2 : nw;
   };
 
   // cache lookup
@@ -990,8 +998,8 @@ hobo_status hobo_autotune(hobo_tensor* t, const uint64_t* x_bits, int64_t B, int
         H(hipMalloc(&bx, (size_t)W * B * 8), "hipMalloc") && H(hipMalloc(&be, (size_t)B * 8), "hipMalloc")) {
       float best = 1e30f;
       int pick = 0;
-      const int cand[4] = {1, 2, 4, 8};
-      for (int q = 0; q < 4 && rc == HOBO_OK; ++q) {
+      const int cand[5] = {1, 2, 4, 8, 16};
+      for (int q = 0; q < 5 && rc == HOBO_OK; ++q) {
         hobo_anneal_params ap{};
         ap.sweeps = 8;
         ap.precision = precision;

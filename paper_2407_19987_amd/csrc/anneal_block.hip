@@ -16,13 +16,18 @@
 // Hc_ab += d_c w_abc.  The chain of states, flip changes and decisions is the
 // same as visiting one variable at a time.
 //
-// Work-group: 16 replicas, NW waves.  Phase 1 (all waves): the field tile is
-// split over the waves by chunks, the 8 pair tiles by tile; every wave streams
-// its chunks through a register ring that runs continuously across blocks
-// and sweeps (loads do not depend on the state).  Phase 2 (wave 0): the 16
+// Work-group: 16 replicas, NW waves in two roles.  Waves 1 .. NW-1 stream:
+// the field tile is split over them by chunks, the 8 pair tiles by tile, and
+// every streaming wave keeps its chunks in flight through a register ring
+// that runs continuously across blocks and sweeps (loads do not depend on the
+// state).  Wave 0 decides: it holds the replicas' energies, stages the
+// block's order-3 table (straight from global memory into LDS) and its
+// Philox uniforms -log(u) while the others stream, then takes the 16
 // decisions, lane = 4 * replica + s, sub-lane s holding bits s, s+4, s+8,
-// s+12 of the block.  Meanwhile another wave stages the next block's
-// coefficient table and its Philox uniforms -log(u).
+// s+12 of the block.  The roles' registers never live at the same time, so
+// the kernel fits four waves per SIMD.  Each block's field list starts with
+// the chunks that read no bit of the block before it in the sweep: the
+// streaming waves compute those while wave 0 still decides that block.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,7 +44,7 @@ constexpr int kSweepWin = 256; // sweeps per launch otherwise (their trace waits
 
 template <int P> struct BSlot {
   BTile<P> b;
-  unsigned long long d;  // run descriptor of this lane's K group
+  unsigned d;            // low word of the run descriptor of this lane's K group (all its fields here)
   int kind;              // 0 chunk, 1 chunk closing its list, 2 padding, 3 end of stream
   int tgt;               // list of the chunk: 0 fields, 1 + t pair tile t
   int ord;               // active-block ordinal of the slot
@@ -48,9 +53,10 @@ template <int P> struct BSlot {
 template <int HT> struct BProd {  // producer cursor (wave-uniform, scalar registers)
   int ord, s, q;         // active-block ordinal, its sweep and block
   int k, padded;         // next slot of the block, the block's padded slot count
-  int cnt_g;             // field chunks of this wave (chunk g0 + k * NW)
-  unsigned g0;
-  int hs[HT], hn[HT];    // pair-tile m of this wave: slots hs .. hs + hn - 1 after the field chunks
+  int pe;                // slots of the early part (a multiple of the ring depth)
+  int ce, cl;            // early / late field chunks of this wave (chunk g0e + k * NS, g0l + k)
+  unsigned g0e, g0l;     // (late chunks are consecutive: g0l + k)
+  int hs[HT], hn[HT];    // pair-tile m of this wave: late slots hs .. hs + hn - 1 after the field chunks
   unsigned hc0[HT];      // its first chunk
 };
 
@@ -67,10 +73,19 @@ __device__ inline int quad_bcast(int v, int o) {
   }
 }
 
+// Lane id read from the hardware counter where it is needed (the asm is not
+// hoisted): values derived from it once and kept across the item loop would
+// hold registers in both roles.
+__device__ inline int lane_id() {
+  int v;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+  return v;
+}
+
 // Eight-monomial mask of a run with at most one prefix variable (all runs of
 // an order <= 3 instance's block lists): the run's byte of the replica's bits,
 // cleared when the prefix bit is 0; constant and padding runs give 1 and 0.
-__device__ inline unsigned run_mask1(unsigned long long d, const unsigned char* rb) {
+__device__ inline unsigned run_mask1(unsigned d, const unsigned char* rb) {
   const unsigned np = (unsigned)(d >> 8) & 0xFFu;
   const unsigned pv = (unsigned)(d >> 16) & 0xFFu;
   const unsigned m = rb[(unsigned)d & 0x1Fu];
@@ -79,31 +94,52 @@ __device__ inline unsigned run_mask1(unsigned long long d, const unsigned char* 
   return np == kRunConst ? 1u : (np == kRunNull ? 0u : v);
 }
 
+// At most 128 VGPRs: four waves per SIMD (one 16-wave group, or several
+// narrower ones, per CU).
 template <int P, int NW>
-__global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void anneal_block_kernel(
+    AnnealParams p) {
+  static_assert(NW >= 2, "one decision wave and at least one streaming wave");
+  // with sixteen waves, wave 1 stages the next block's table and uniforms
+  // while wave 0 decides; narrower groups let wave 0 stage its own block
+  constexpr bool STAGER = NW == 16;
+  constexpr int NS = NW - 1 - (STAGER ? 1 : 0);  // streaming waves (the last NS)
+  constexpr int W0 = NW - NS;                    // first streaming wave
+  constexpr int NBUF = STAGER ? 2 : 1;           // buffers of the staged table and uniforms
   constexpr int D = kRing;
   constexpr int RPC = PT<P>::RPC;
   constexpr int TB = P == P_FP32 ? 2048 : (P == P_BF16X2 ? 2048 : 3072);
-  constexpr int HT = (kPairTiles + NW - 1) / NW;  // pair tiles per wave
+  constexpr int HT = (kPairTiles + NS - 1) / NS;  // pair tiles per streaming wave
   __shared__ Luts L;
   __shared__ unsigned long long sbits[64];  // 16 replicas x 32 bytes
   __shared__ unsigned long long sbest[64];
-  __shared__ float sG[NW][16][17];          // per-wave partial fields [rep][bit]
-  __shared__ float sH[128][17];             // pair couplings [pair][rep]
-  __shared__ __attribute__((aligned(16))) float sC[2][4096];  // order-3 table of the block [c][a][b]
-  __shared__ double sL[2][16][17];          // -log(u) [rep][bit]
+  // per-streaming-wave partial fields, [rep][4 * sub + i] holds bit sub + 4 i
+  // (two buffers: a block's early chunks run while the decisions of the one
+  // before it still read its fields)
+  __shared__ __attribute__((aligned(16))) float sG[2][NS][16][16];
+  __shared__ __attribute__((aligned(16))) float sH[16][16][16];  // pair couplings [rep][a][b], b < a
+  __shared__ unsigned short sPC[128];  // pair column -> (a << 8) | b (unused columns -> 0)
+  __shared__ __attribute__((aligned(16))) float sC[NBUF][4096];  // order-3 table of the block [c][a][b]
+  __shared__ double sL[NBUF][16][17];       // -log(u) [rep][bit]
   __shared__ BlockMeta sBM[kMaxVars / kBlockBits];
   __shared__ unsigned short sAM[kMaskWin][kMaxVars / kBlockBits];  // attempted bits per (sweep, block)
   __shared__ unsigned short sAL[kMaskWin * (kMaxVars / kBlockBits)];  // active (sweep, block), stream order
   __shared__ int sNA;                                                  // their number
+  // late field chunks of each (block, streaming wave): first (offset in the
+  // late part of the list) and count; waves holding pair tiles take fewer
+  __shared__ __attribute__((aligned(4))) unsigned short sLF[kMaxVars / kBlockBits][NS][2];
   __shared__ double strace[kSweepWin];  // per-sweep tile minima, written back after the launch's sweeps
 
   build_luts(&L);
+  for (int e = threadIdx.x; e < 128; e += blockDim.x) {
+    unsigned v = 0;
+    for (int a = 1; a < 16; ++a)
+      for (int b = 0; b < a; ++b)
+        if (pair_col(b, a) == e) v = (unsigned)(a << 8 | b);
+    sPC[e] = (unsigned short)v;
+  }
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave index, uniform
-  const int g = lane >> 4, j = lane & 15;
-  // phase-2 layout
-  const int rep = lane >> 2, sub = lane & 3;
 
   for (int it = blockIdx.x; it < p.n_items; it += gridDim.x) {
     __syncthreads();
@@ -130,13 +166,14 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
       load_bits(sbits, I.x, I.W, I.B, r0, 16, lane);
       load_bits(sbest, p.cont ? I.best_x : I.x, I.W, I.B, r0, 16, lane);
     }
+    // the streaming waves only ever add their results to zeroed outputs;
+    // wave 0 clears each output again once it has read it
+    for (int e = threadIdx.x; e < 2 * NS * 64; e += blockDim.x)
+      reinterpret_cast<f4*>(&sG[0][0][0][0])[e] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int e = threadIdx.x; e < 1024; e += blockDim.x)
+      reinterpret_cast<f4*>(&sH[0][0][0])[e] = f4{0.f, 0.f, 0.f, 0.f};
     __syncthreads();
 
-    auto block_bits = [&](int s, int q) -> unsigned {
-      const unsigned nb = __builtin_amdgcn_readfirstlane(sBM[q].nbits);
-      const unsigned full = (1u << nb) - 1u;
-      return masked ? __builtin_amdgcn_readfirstlane((unsigned)sAM[s - p.s_begin][q]) & full : full;
-    };
     // the active blocks of the launch, in stream order: every (sweep, block)
     // without masks; with masks the list of those with an attempted bit
     if (masked) {
@@ -156,6 +193,35 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
       }
       __syncthreads();
     }
+    // balanced late parts: quota Q per wave of late field chunks plus pair
+    // chunks; wave v takes max(0, Q - its pair chunks) late field chunks in
+    // order, the last wave whatever remains
+    for (int e = threadIdx.x; e < NB * NS; e += blockDim.x) {
+      const int q = e / NS, v = e - q * NS;
+      const BlockMeta& m = sBM[q];
+      const int ne = masked ? 0 : (int)m.nearly;
+      const int nl = (int)m.nchunks[0] - ne;
+      auto pairs_of = [&](int wv) {
+        int c = 0;
+        for (int t = wv; t < (int)m.npt; t += NS) c += (int)m.nchunks[1 + t];
+        return c;
+      };
+      int tot = nl;
+      for (int t = 0; t < (int)m.npt; ++t) tot += (int)m.nchunks[1 + t];
+      const int quota = (tot + NS - 1) / NS;
+      int off = 0;
+      for (int wv = 0; wv < v; ++wv) {
+        const int f = quota - pairs_of(wv);
+        off += f > 0 ? f : 0;
+      }
+      off = off < nl ? off : nl;
+      int f = quota - pairs_of(v);
+      f = f > 0 ? f : 0;
+      f = v == NS - 1 ? nl - off : (f < nl - off ? f : nl - off);
+      sLF[q][v][0] = (unsigned short)off;
+      sLF[q][v][1] = (unsigned short)f;
+    }
+    __syncthreads();
     const int nact = masked ? __builtin_amdgcn_readfirstlane(sNA) : (p.s_end - p.s_begin) * NB;
     // (sweep, block) of active ordinal o, given those of o - 1
     auto step_block = [&](int o, int& s, int& q) {
@@ -168,208 +234,105 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
         ++s;
       }
     };
+    int cs = p.s_begin, cq = 0;  // sweep and block of active ordinal 0
+    if (masked && nact > 0) step_block(0, cs, cq);
 
-    auto stage_block = [&](int s, int q, int bf, int tid, int nthr, bool do_u) {
-      const u4* src = reinterpret_cast<const u4*>(I.triples + (size_t)q * 4096);
-      u4* dst = reinterpret_cast<u4*>(sC[bf]);
-      for (int e = tid; e < 1024; e += nthr) dst[e] = gld(src + e);
-      if (do_u && tid < 64) {
-        // lane (rep, grp) draws the four words of bits 16q + 4 grp .. +3
-        const int rp = tid >> 2, gp = tid & 3;
-        U64x4 o = philox((unsigned long long)(r0 + rp), (unsigned long long)s,
-                         (unsigned long long)(4 * q + gp), 0ull, p.seed, I.inst_id);
+    // the order-3 table of block (s, q) and the uniforms -log(u) of its
+    // 16 x 16 decisions into buffer bf, by one wave; returns once they are in LDS
+    auto stage = [&](int s, int q, int bf) {
+      const int lane = lane_id();
+      const int rep = lane >> 2, sub = lane & 3;
+      // the table goes straight from global memory into LDS (no registers)
+      const float* src = I.triples + (size_t)q * 4096;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double u = (double)(o.w[e] >> 11) * 0x1.0p-53;
-          sL[bf][rp][4 * gp + e] = u > 0.0 ? -log(u) : INFINITY;
-        }
+      for (int e = 0; e < 16; ++e)
+        __builtin_amdgcn_global_load_lds(src + 256 * e + 4 * lane,
+                                         (__attribute__((address_space(3))) void*)(&sC[bf][256 * e]), 16, 0, 0);
+      // lane (rep, grp) draws the four words of bits 16q + 4 grp .. +3
+      U64x4 o = philox((unsigned long long)(r0 + rep), (unsigned long long)s, (unsigned long long)(4 * q + sub),
+                       0ull, p.seed, I.inst_id);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double u = (double)(o.w[e] >> 11) * 0x1.0p-53;
+        sL[bf][rep][4 * sub + e] = u > 0.0 ? -log(u) : INFINITY;
       }
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the table is in LDS
     };
 
-    // ---- state of the 16 replicas (wave 0, phase-2 layout)
-    const long long myrow = r0 + rep;
-    const bool live = myrow < I.B;
-    double E = 0.0, bestE = 0.0;
-    if (w == 0 && live) {
-      E = gld(I.e_track + myrow);
-      bestE = p.cont ? gld(I.best_track + myrow) : E;
-    }
-
-    // ---- producer: straight-line, scalar; block changes every `padded` slots
-    BProd<HT> pr{};
-    auto setup_block = [&]() {
-      const BlockMeta& m = sBM[pr.q];
-      const int ng = __builtin_amdgcn_readfirstlane((int)m.nchunks[0]);
-      const int npt = __builtin_amdgcn_readfirstlane((int)m.npt);
-      pr.cnt_g = ng > w ? (ng - w + NW - 1) / NW : 0;
-      pr.g0 = __builtin_amdgcn_readfirstlane(m.chunk0[0]) + (unsigned)w;
-      int tot = 0;
-#pragma unroll
-      for (int mm = 0; mm < HT; ++mm) {
-        const int t = w + mm * NW;
-        const bool ok = t < npt;
-        pr.hs[mm] = tot;
-        pr.hn[mm] = ok ? __builtin_amdgcn_readfirstlane((int)m.nchunks[1 + (ok ? t : 0)]) : 0;
-        pr.hc0[mm] = ok ? __builtin_amdgcn_readfirstlane(m.chunk0[1 + (ok ? t : 0)]) : 0u;
-        tot += pr.hn[mm];
+    // Every role passes two work-group barriers per active block: A when the
+    // block's fields and couplings are in LDS, B when its decisions are.  The
+    // streaming waves run a block's early part (field chunks that read no bit
+    // of the block before) between A and B of the block before.
+    if (w == 0) {
+      // ================= decision wave: replica state, decisions
+      // (raised priority: its chain of decisions is the one the others wait for)
+      __builtin_amdgcn_s_setprio(2);
+      const int lane = lane_id();
+      const int rep = lane >> 2, sub = lane & 3;
+      const long long myrow = r0 + rep;
+      const bool live = myrow < I.B;
+      double E = 0.0, bestE = 0.0;
+      if (live) {
+        E = gld(I.e_track + myrow);
+        bestE = p.cont ? gld(I.best_track + myrow) : E;
       }
-      tot += pr.cnt_g;
-      pr.padded = tot <= D ? D : (tot + D - 1) / D * D;
-      pr.k = 0;
-    };
-    // the producer enters its next active block; its slot counts are whole
-    // rounds of D, so this happens only between rounds
-    auto advance = [&]() {
-      if (pr.k == pr.padded) {
-        ++pr.ord;
-        if (pr.ord < nact) {
-          step_block(pr.ord, pr.s, pr.q);
-          setup_block();
-        }
-        pr.k = 0;
-      }
-    };
-    auto issue = [&](BSlot<P>& sl) {
-      const int k = pr.k;
-      unsigned c = 0;
-      int kind = 2, tgt = 0;
-      if (k < pr.cnt_g) {
-        c = pr.g0 + (unsigned)(k * NW);
-        kind = k == pr.cnt_g - 1 ? 1 : 0;
-      } else {
-        const int kk = k - pr.cnt_g;
-#pragma unroll
-        for (int mm = 0; mm < HT; ++mm)
-          if (kk >= pr.hs[mm] && kk < pr.hs[mm] + pr.hn[mm]) {
-            c = pr.hc0[mm] + (unsigned)(kk - pr.hs[mm]);
-            kind = kk == pr.hs[mm] + pr.hn[mm] - 1 ? 1 : 0;
-            tgt = 1 + w + mm * NW;
-          }
-      }
-      pr.k = k + 1;
-      if (pr.ord >= nact) {  // past the last block
-        kind = 3;
-        c = 0;
-      }
-      sl.kind = __builtin_amdgcn_readfirstlane(kind);
-      sl.tgt = __builtin_amdgcn_readfirstlane(tgt);
-      sl.ord = __builtin_amdgcn_readfirstlane(pr.ord);
-      unsigned tix = kind <= 1 ? c + 1u : 0u;
-      tix = tix < I.n_tiles ? tix : 0u;  // never outside the tile buffer
-      load_tile<P>(sl.b, I.tiles + (size_t)tix * TB, lane);
-      sl.d = gld(I.runs + (size_t)c * RPC + g);
-    };
-
-    pr.ord = 0;
-    pr.s = p.s_begin;
-    pr.q = 0;
-    if (nact > 0) {
-      if (masked) step_block(0, pr.s, pr.q);
-      setup_block();
-    }
-    int co = 0, cs = pr.s, cq = pr.q;  // consumer: active ordinal, sweep, block
-    int bf = 0;                        // buffer of the consumer block's table and uniforms
-    if (co < nact) stage_block(cs, cq, 0, threadIdx.x, blockDim.x, true);
-    BSlot<P> ring[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) issue(ring[d]);
-    __syncthreads();
-
-    AccT<P> acc;
-    acc_zero<P>(acc);
-    const unsigned char* rb = reinterpret_cast<const unsigned char*>(sbits) + j * 32;
-    int s_prev = p.s_begin;  // sweeps before s_prev are closed
-
-    auto end_sweep = [&](int s) {
-      if (w == 0) {
+      int s_prev = p.s_begin;  // sweeps before s_prev are closed
+      auto end_sweep = [&](int s) {
         if (live && sub == 0 && E < bestE) {
           bestE = E;
           for (int qq = 0; qq < 4; ++qq) sbest[rep * 4 + qq] = sbits[rep * 4 + qq];
         }
         double v = live ? bestE : INFINITY;
         for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-        // kept in LDS: a global store here would make the stream's counted waits imprecise
         if (lane == 0) strace[s - p.s_begin] = v;
-      }
-    };
-
-    while (co < nact) {
-      while (s_prev < cs) end_sweep(s_prev++);
-      const int q = cq;
-      const unsigned amask = block_bits(cs, q);
-      const BlockMeta& bmq = sBM[q];
-      // ---- phase 1: zero this wave's outputs, then stream the block's chunks
-      for (int e = lane; e < 256; e += 64) sG[w][e >> 4][e & 15] = 0.0f;
-      for (int t = w; t < (int)bmq.npt; t += NW)
-        for (int e = lane; e < 256; e += 64) sH[16 * t + (e & 15)][e >> 4] = 0.0f;
-      // whole rounds of D slots belong to one block (its slot count is padded)
-      while (ring[0].ord == co) {
-        advance();
-        // one round: the operand of slot d + 1 is generated before the
-        // matrix-core work of slot d, so its LDS reads overlap that work
-        auto gen = [&](const BSlot<P>& sl) {
-          // every slot's registers are consumed on every path (padding slots
-          // multiply a zero operand), so the counted waits stay exact
-          const unsigned m1 = run_mask1(sl.d, rb);
-          const unsigned msk = sl.kind <= 1 ? m1 : 0u;
-          AOp<P> a;
-          if constexpr (P == P_FP32) {
-            a.v = u4{msk, 0u, 0u, 0u};
-          } else {
-            a.v = L.bf16[msk];
-          }
-          return a;
-        };
-        AOp<P> an = gen(ring[0]);
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          BSlot<P>& sl = ring[d];
-          const AOp<P> a = an;
-          if (d + 1 < D) an = gen(ring[d + 1 < D ? d + 1 : 0]);
-          mma<P>(acc, a, sl.b);
-          if (sl.kind == 1) {  // the chunk closes its list: fields [rep][bit], pairs [pair][rep]
-            if (sl.tgt == 0) {
-#pragma unroll
-              for (int r = 0; r < 4; ++r) sG[w][4 * g + r][j] = acc.v[r];
-            } else {
-#pragma unroll
-              for (int r = 0; r < 4; ++r) sH[16 * (sl.tgt - 1) + j][4 * g + r] = acc.v[r];
-            }
-            acc_zero<P>(acc);
-          }
-          issue(sl);
-        }
-      }
-      lds_barrier();
-      // ---- the next active block, for the staging wave
-      int ns = cs, nq = cq;
-      if (co + 1 < nact) step_block(co + 1, ns, nq);
-      if (w == 0) {
-        // ---- phase 2: sixteen sequential decisions
+      };
+      for (int co = 0; co < nact; ++co) {
+        if (co > 0) step_block(co, cs, cq);
+        while (s_prev < cs) end_sweep(s_prev++);
+        const int q = cq;
+        // per-block lane layout (its LDS addresses are not kept across blocks)
+        const int lane = lane_id();
+        const int rep = lane >> 2, sub = lane & 3;
+        const unsigned nbq = __builtin_amdgcn_readfirstlane(sBM[q].nbits);
+        const unsigned full = (1u << nbq) - 1u;
+        const unsigned amask =
+            masked ? __builtin_amdgcn_readfirstlane((unsigned)sAM[cs - p.s_begin][q]) & full : full;
+        const int bf = STAGER ? (co & 1) : 0;
+        // while the streaming waves compute the block's fields: its table and uniforms
+        if (!STAGER) stage(cs, q, 0);
         const double beta = gld(p.beta + (cs - p.s_first));
+        lds_barrier();  // A
+        // ---- sixteen sequential decisions, sub-lane s holding bits s, s+4, s+8, s+12
         float gq[4];
         float hc[4][16];
         double lu[4];
+        {
+          const int gb = co & 1;
+          f4 acc4 = *reinterpret_cast<const f4*>(&sG[gb][0][rep][4 * sub]);
+#pragma unroll
+          for (int ww = 1; ww < NS; ++ww) acc4 += *reinterpret_cast<const f4*>(&sG[gb][ww][rep][4 * sub]);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) gq[i] = acc4[i];
+#pragma unroll
+          for (int ww = 0; ww < NS; ++ww) reinterpret_cast<f4*>(&sG[gb][ww][0][0])[lane] = f4{0.f, 0.f, 0.f, 0.f};
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int a = sub + 4 * i;
-          float v = 0.0f;
-#pragma unroll
-          for (int ww = 0; ww < NW; ++ww) v += sG[ww][rep][a];
-          gq[i] = v;
           lu[i] = sL[bf][rep][a];
 #pragma unroll
           for (int b = 0; b < 16; ++b) {
             if (b < 4 * i + 3) {
-              const int pc = b < a ? pair_col(b, a) : 0;
-              const float h = sH[pc][rep];
+              const float h = sH[rep][a][b];
               hc[i][b] = b < a ? h : 0.0f;
             }
           }
         }
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          reinterpret_cast<f4*>(&sH[0][0][0])[64 * e + lane] = f4{0.f, 0.f, 0.f, 0.f};
         unsigned char* myb = reinterpret_cast<unsigned char*>(sbits) + rep * 32 + 2 * q;
         unsigned xb = (unsigned)myb[0] | ((unsigned)myb[1] << 8);
-        const float* tri = sC[bf];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           if (!((amask >> c) & 1u)) continue;  // not attempted (or past the last variable)
@@ -392,7 +355,7 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
               if (4 * i + 3 > c) {
                 const int a = sub + 4 * i;
                 gq[i] = fmaf(dl, hc[i][c], gq[i]);
-                const float* row = tri + (c * 16 + a) * 16;
+                const float* row = &sC[bf][(c * 16 + a) * 16];
 #pragma unroll
                 for (int b = 0; b < 16; ++b)
                   if (b > c && b < 4 * i + 3) hc[i][b] = fmaf(dl, row[b], hc[i][b]);
@@ -404,25 +367,11 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
           myb[0] = (unsigned char)(xb & 0xFFu);
           myb[1] = (unsigned char)(xb >> 8);
         }
-        if (NW == 1 && co + 1 < nact) stage_block(ns, nq, bf ^ 1, lane, 64, true);
-      } else if (co + 1 < nact) {
-        // the other waves stage the next block's triple table and uniforms
-        stage_block(ns, nq, bf ^ 1, threadIdx.x - 64, 64 * (NW - 1), true);
+        lds_barrier();  // B
       }
-      // every load issued so far has landed (the ring's were issued before
-      // phase 2): the stream loop then starts from a known count of
-      // outstanding loads and keeps its ring in flight
-      __builtin_amdgcn_s_waitcnt(0x0F70);
-      lds_barrier();
-      bf ^= 1;
-      ++co;
-      cs = ns;
-      cq = nq;
-    }
-    while (s_prev < p.s_end) end_sweep(s_prev++);
+      while (s_prev < p.s_end) end_sweep(s_prev++);
 
-    // write back (wave 0)
-    if (w == 0) {
+      // write back
       if (I.trace_part)
         for (int s = p.s_begin + lane; s < p.s_end; s += 64)
           I.trace_part[(size_t)item.tile16 * p.sweeps + (s - p.s_first)] = strace[s - p.s_begin];
@@ -436,6 +385,170 @@ __global__ __launch_bounds__(64 * NW) void anneal_block_kernel(AnnealParams p) {
         I.e_track[myrow] = E;
         I.best_track[myrow] = bestE;
       }
+      __builtin_amdgcn_s_setprio(0);
+    } else if (STAGER && w == 1) {
+      // ================= staging wave: block o + 1 while block o is decided
+      int ss = cs, sq = cq;
+      if (nact > 0) stage(ss, sq, 0);
+      for (int co = 0; co < nact; ++co) {
+        lds_barrier();  // A
+        if (co + 1 < nact) {
+          step_block(co + 1, ss, sq);
+          stage(ss, sq, (co + 1) & 1);
+        }
+        lds_barrier();  // B
+      }
+    } else {
+      // ================= streaming waves: the block's fields and couplings
+      const int ws = w - W0;
+      const int lane = lane_id();
+      const int g = lane >> 4, j = lane & 15;
+      // producer: straight-line, scalar; block changes every `padded` slots
+      BProd<HT> pr{};
+      auto setup_block = [&]() {
+        const BlockMeta& m = sBM[pr.q];
+        const int npt = __builtin_amdgcn_readfirstlane((int)m.npt);
+        // with attempt masks the block before is not known when packing: no early part
+        const int ne = masked ? 0 : __builtin_amdgcn_readfirstlane((int)m.nearly);
+        // early chunks in turn (chunk g0e + k NS), late ones a contiguous range
+        pr.ce = ne > ws ? (ne - ws + NS - 1) / NS : 0;
+        const unsigned lf = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const unsigned*>(&sLF[pr.q][ws][0]));
+        pr.cl = (int)(lf >> 16);
+        const unsigned c0 = __builtin_amdgcn_readfirstlane(m.chunk0[0]);
+        pr.g0e = c0 + (unsigned)ws;
+        pr.g0l = c0 + (unsigned)ne + (lf & 0xFFFFu);
+        int tot = 0;
+#pragma unroll
+        for (int mm = 0; mm < HT; ++mm) {
+          const int t = ws + mm * NS;
+          const bool ok = t < npt;
+          pr.hs[mm] = tot;
+          pr.hn[mm] = ok ? __builtin_amdgcn_readfirstlane((int)m.nchunks[1 + (ok ? t : 0)]) : 0;
+          pr.hc0[mm] = ok ? __builtin_amdgcn_readfirstlane(m.chunk0[1 + (ok ? t : 0)]) : 0u;
+          tot += pr.hn[mm];
+        }
+        tot += pr.cl;
+        pr.pe = (pr.ce + D - 1) / D * D;
+        const int pl = (tot + D - 1) / D * D;
+        pr.padded = pr.pe + (pr.pe + pl == 0 ? D : pl);
+        pr.k = 0;
+      };
+      // the producer enters its next active block; its slot counts are whole
+      // rounds of D, so this happens only between rounds
+      auto advance = [&]() {
+        if (pr.k == pr.padded) {
+          ++pr.ord;
+          if (pr.ord < nact) {
+            step_block(pr.ord, pr.s, pr.q);
+            setup_block();
+          }
+          pr.k = 0;
+        }
+      };
+      auto issue = [&](BSlot<P>& sl) {
+        const int k = pr.k;
+        unsigned c = 0;
+        int kind = 2, tgt = 0;
+        const int part = k < pr.pe ? 0 : 1;
+        if (k < pr.pe) {  // early field chunks; the last closes the list when no late ones follow
+          if (k < pr.ce) {
+            c = pr.g0e + (unsigned)(k * NS);
+            kind = (k == pr.ce - 1 && pr.cl == 0) ? 1 : 0;
+          }
+        } else if (k - pr.pe < pr.cl) {
+          const int kl = k - pr.pe;
+          c = pr.g0l + (unsigned)kl;
+          kind = kl == pr.cl - 1 ? 1 : 0;
+        } else {
+          const int kk = k - pr.pe - pr.cl;
+#pragma unroll
+          for (int mm = 0; mm < HT; ++mm)
+            if (kk >= pr.hs[mm] && kk < pr.hs[mm] + pr.hn[mm]) {
+              c = pr.hc0[mm] + (unsigned)(kk - pr.hs[mm]);
+              kind = kk == pr.hs[mm] + pr.hn[mm] - 1 ? 1 : 0;
+              tgt = 1 + ws + mm * NS;
+            }
+        }
+        pr.k = k + 1;
+        if (pr.ord >= nact) {  // past the last block
+          kind = 3;
+          c = 0;
+        }
+        sl.kind = __builtin_amdgcn_readfirstlane(kind);
+        sl.tgt = __builtin_amdgcn_readfirstlane(tgt);
+        sl.ord = __builtin_amdgcn_readfirstlane(2 * pr.ord + part);  // (block, part)
+        unsigned tix = kind <= 1 ? c + 1u : 0u;
+        tix = tix < I.n_tiles ? tix : 0u;  // never outside the tile buffer
+        load_tile<P>(sl.b, I.tiles + (size_t)tix * TB, lane);
+        sl.d = gld(reinterpret_cast<const unsigned*>(I.runs + (size_t)c * RPC + g));
+      };
+
+      pr.ord = 0;
+      pr.s = cs;
+      pr.q = cq;
+      if (nact > 0) setup_block();
+      BSlot<P> ring[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) issue(ring[d]);
+
+      AccT<P> acc;
+      acc_zero<P>(acc);
+      const unsigned char* rb = reinterpret_cast<const unsigned char*>(sbits) + j * 32;
+      // one round of D slots: the operand of slot d + 1 is generated before
+      // the matrix-core work of slot d, so its LDS reads overlap that work
+      auto round = [&](float* myG) {
+        advance();
+        auto gen = [&](const BSlot<P>& sl) {
+          // every slot's registers are consumed on every path (padding slots
+          // multiply a zero operand), so the counted waits stay exact
+          const unsigned m1 = run_mask1(sl.d, rb);
+          const unsigned msk = sl.kind <= 1 ? m1 : 0u;
+          AOp<P> a;
+          if constexpr (P == P_FP32) {
+            a.v = u4{msk, 0u, 0u, 0u};
+          } else {
+            a.v = L.bf16[msk];
+          }
+          return a;
+        };
+        AOp<P> an = gen(ring[0]);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          BSlot<P>& sl = ring[d];
+          const AOp<P> a = an;
+          if (d + 1 < D) an = gen(ring[d + 1 < D ? d + 1 : 0]);
+          mma<P>(acc, a, sl.b);
+          if (sl.kind == 1) {  // the chunk closes its list: fields [rep][sub][i], pairs [rep][a][b]
+            if (sl.tgt == 0) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) myG[16 * r] = acc.v[r];
+            } else {
+              const unsigned ab = sPC[16 * (sl.tgt - 1) + j];
+              float* dst = &sH[4 * g][ab >> 8][ab & 0xFFu];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) dst[256 * r] = acc.v[r];
+            }
+            acc_zero<P>(acc);
+          }
+          issue(sl);
+        }
+      };
+      for (int co = 0; co < nact; ++co) {
+        if (co > 0) step_block(co, cs, cq);
+        // this lane's field outputs in the block's buffer, rebuilt from the
+        // lane id every block (kept live across the block loop, the address
+        // would be spilled, and reloading it would drain the load ring)
+        const int ln = lane_id();
+        float* myG = &sG[co & 1][ws][0][0] + (ln >> 4) * 64 + 4 * (ln & 3) + ((ln >> 2) & 3);
+        // ---- early part: field chunks that read no bit of the block before,
+        // while that block's decisions are taken (whole rounds per part)
+        while (ring[0].ord == 2 * co) round(myG);
+        if (co > 0) lds_barrier();  // B of the block before
+        // ---- late part: the other field chunks and the pair tiles
+        while (ring[0].ord == 2 * co + 1) round(myG);
+        lds_barrier();  // A
+      }
+      if (nact > 0) lds_barrier();  // B of the last block
     }
   }
 }
@@ -452,9 +565,9 @@ int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipS
     launch_block_t<PV, NWV>(ap, nblk, st);   \
     return 0;                                \
   }
-  HOBO_AB(P_FP32, 1) HOBO_AB(P_FP32, 2) HOBO_AB(P_FP32, 4) HOBO_AB(P_FP32, 8)
-  HOBO_AB(P_BF16X2, 1) HOBO_AB(P_BF16X2, 2) HOBO_AB(P_BF16X2, 4) HOBO_AB(P_BF16X2, 8)
-  HOBO_AB(P_BF16X3, 1) HOBO_AB(P_BF16X3, 2) HOBO_AB(P_BF16X3, 4) HOBO_AB(P_BF16X3, 8)
+  HOBO_AB(P_FP32, 2) HOBO_AB(P_FP32, 4) HOBO_AB(P_FP32, 8) HOBO_AB(P_FP32, 16)
+  HOBO_AB(P_BF16X2, 2) HOBO_AB(P_BF16X2, 4) HOBO_AB(P_BF16X2, 8) HOBO_AB(P_BF16X2, 16)
+  HOBO_AB(P_BF16X3, 2) HOBO_AB(P_BF16X3, 4) HOBO_AB(P_BF16X3, 8) HOBO_AB(P_BF16X3, 16)
 #undef HOBO_AB
   return -1;
 }

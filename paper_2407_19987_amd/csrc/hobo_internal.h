@@ -80,6 +80,8 @@ struct BlockMeta {
   uint32_t nchunks[kBlockLists];  // chunks of each list
   uint32_t nbits;                 // variables in the block (16, fewer in the last)
   uint32_t npt;                   // pair lists in use (ceil(C(nbits,2) / 16))
+  uint32_t nearly;                // leading chunks of the field list that read no bit of the
+                                  // block before it in a sweep (block q-1, or the last for q = 0)
 };
 // pair (a, b), a < b < 16, of a block -> its column among the 120 pair columns
 __host__ __device__ inline int pair_col(int a, int b) { return b * (b - 1) / 2 + a; }

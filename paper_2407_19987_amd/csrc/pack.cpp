@@ -419,10 +419,37 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
       BlockMeta& b = bm[(size_t)q];
       b.nbits = (uint32_t)nbits;
       b.npt = (uint32_t)npt;
+      // The field list's runs that read no bit of the previous block of the
+      // sweep come first: the kernel computes them while that block's
+      // decisions are still being taken.
+      const int p0 = ((q + nb - 1) % nb) * kBlockBits;
+      auto reads_prev = [&](uint64_t d) {
+        const uint32_t np = (uint32_t)(d >> 8) & 0xFFu;
+        if (np == kRunConst || np == kRunNull) return false;
+        const int lo = (int)(d & 0xFFu) * 8;  // the run's eight variables lo .. lo+7
+        if (lo + 8 > p0 && lo < p0 + kBlockBits) return true;
+        for (uint32_t j = 0; j < np; ++j) {
+          const int v = (int)((d >> (16 + 8 * j)) & 0xFFu);
+          if (v >= p0 && v < p0 + kBlockBits) return true;
+        }
+        return false;
+      };
       for (int li = 0; li < kBlockLists; ++li) {
         b.chunk0[li] = (uint32_t)po.chunks.size();
-        if (li == 0 || li - 1 < npt) {
-          RunMat& r = li == 0 ? rg : rh[(size_t)(li - 1)];
+        if (li == 0) {
+          std::vector<int> early, late;
+          for (int r : run_order(rg)) (reads_prev(rg.desc[(size_t)r]) ? late : early).push_back(r);
+          if (!early.empty()) {
+            st = pack_runs(rg, early, prec, false, 1, &po, err, true);
+            if (st) return st;
+          }
+          b.nearly = (uint32_t)po.chunks.size() - b.chunk0[0];
+          if (!late.empty()) {
+            st = pack_runs(rg, late, prec, false, 1, &po, err, true);
+            if (st) return st;
+          }
+        } else if (li - 1 < npt) {
+          RunMat& r = rh[(size_t)(li - 1)];
           st = pack_runs(r, run_order(r), prec, false, 1, &po, err, true);
           if (st) return st;
         }

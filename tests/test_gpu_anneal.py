@@ -92,11 +92,13 @@ def test_trajectory_identity_int3(env, prec, algo):
 
 
 @pytest.mark.parametrize("n,k,dens,nw", [(5, 3, 1.0, 1), (16, 2, 1.0, 2), (37, 3, 0.6, 4), (64, 3, 0.25, 8),
-                                         (130, 2, 0.4, 4), (100, 1, 1.0, 2), (48, 3, 0.5, 1)])
+                                         (130, 2, 0.4, 4), (100, 1, 1.0, 2), (48, 3, 0.5, 1),
+                                         (150, 3, 0.3, 16), (29, 3, 1.0, 16)])
 def test_blocked_trajectory_identity(env, n, k, dens, nw):
     """The blocked annealer (fields and pair couplings per 16-bit block, the
     block's sixteen decisions resolved in registers) runs the oracle's chain:
-    ragged last blocks, every order up to 3, one to eight waves."""
+    ragged last blocks, every order up to 3, one (taken as two) to sixteen
+    waves."""
     hobo, _ = env
     terms = _int_instance(100 + n, n, k, lo=-4, hi=4, dens=dens)
     c = oracle.canonicalize(terms)
