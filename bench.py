@@ -293,7 +293,7 @@ def main():
         prof = os.path.join(ROOT, "profiles", "anneal_block_traffic_order3_n128_b4096.md")
         txt = open(prof).read()
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        row = re.search(r"`anneal_block_kernel<1, 8>` \(BF16x2\) \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|", txt)
+        row = re.search(r"`anneal_block_kernel<1, \d+>` \(BF16x2\) \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|", txt)
         fs = float(re.search(r"FETCH x ([0-9.]+)", txt).group(1))
         ws = float(re.search(r"WRITE x ([0-9.]+)", txt).group(1))
         if (digest in txt and row and args.precision == "bf16x2" and B == REPLICAS and S == SWEEPS

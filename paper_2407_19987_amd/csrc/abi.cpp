@@ -592,12 +592,13 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     return pl;
   };
   // blocked kernel width (one decision wave plus streaming waves, so at
-  // least 2): one 16-replica group per CU wants all sixteen waves, two
-  // groups per CU eight each
+  // least 2): one 16-replica group per CU wants all sixteen waves (with a
+  // staging wave), two groups per CU eight each; the three-term split keeps
+  // sixteen (its eight-wave form runs short of registers)
   auto blk_waves = [&](int64_t tiles) {
     int nw = P.waves_per_block;
     if (!nw && n_instances == 1) nw = tuned_shape(tensors[0]->t, hobo::TK_ANNEAL, P.precision, replicas[0]);
-    if (!nw) nw = tiles <= 256 ? 16 : 8;
+    if (!nw) nw = (tiles <= 256 || P.precision == HOBO_PREC_BF16X3) ? 16 : 8;
     return nw < 2 ? 2 : nw;
   };
 
