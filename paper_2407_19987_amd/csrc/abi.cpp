@@ -785,6 +785,20 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     }
     (void)max_ct;
     (void)max_nw;
+    // the blocked kernel's work schedule for each plan's group width
+    for (const hobo::AnnealPlan& pl : ne.plans) {
+      if (pl.n_blk == 0) continue;
+      for (int j = pl.inst0; j < pl.inst0 + pl.ninst; ++j) {
+        if (!blocked[(size_t)j]) continue;
+        const hobo::BlockSchedule* bs = nullptr;
+        if (int s = hobo::get_block_schedule(&tensors[j]->t, pks[(size_t)j], pl.nw_blk, pl.masked != 0, &bs, &err)) {
+          (void)hipFree(ne.work);
+          return fail(s, err);
+        }
+        inst[(size_t)j].sched = bs->d_words;
+        inst[(size_t)j].sched_hdr = bs->d_hdr;
+      }
+    }
     ne.tb.d_inst = reinterpret_cast<hobo::AnnealInstDev*>(wb + off_inst);
     ne.tb.d_items = reinterpret_cast<hobo::AnnealItem*>(wb + off_items);
     ne.tb.d_small = reinterpret_cast<hobo::InstSmall*>(wb + off_small);

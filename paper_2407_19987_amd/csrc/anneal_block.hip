@@ -50,14 +50,11 @@ template <int P> struct BSlot {
   int ord;               // active-block ordinal of the slot
 };
 
-template <int HT> struct BProd {  // producer cursor (wave-uniform, scalar registers)
-  int ord, s, q;         // active-block ordinal, its sweep and block
-  int k, padded;         // next slot of the block, the block's padded slot count
-  int pe;                // slots of the early part (a multiple of the ring depth)
-  int ce, cl;            // early / late field chunks of this wave (chunk g0e + k * NS, g0l + k)
-  unsigned g0e, g0l;     // (late chunks are consecutive: g0l + k)
-  int hs[HT], hn[HT];    // pair-tile m of this wave: late slots hs .. hs + hn - 1 after the field chunks
-  unsigned hc0[HT];      // its first chunk
+struct BProd {  // producer cursor (wave-uniform, scalar registers)
+  int ord, s, q;   // active-block ordinal, its sweep and block
+  int k;           // next slot of the block
+  int pe, padded;  // the block's early slots and all its slots (whole rounds)
+  unsigned off;    // first slot word of the block in the schedule
 };
 
 template <int CTRL> __device__ inline int dpp_i(int v) {
@@ -109,7 +106,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   constexpr int D = kRing;
   constexpr int RPC = PT<P>::RPC;
   constexpr int TB = P == P_FP32 ? 2048 : (P == P_BF16X2 ? 2048 : 3072);
-  constexpr int HT = (kPairTiles + NS - 1) / NS;  // pair tiles per streaming wave
+  static_assert(D == kBlockRing, "the schedule is built in rounds of the ring depth");
   __shared__ Luts L;
   __shared__ unsigned long long sbits[64];  // 16 replicas x 32 bytes
   __shared__ unsigned long long sbest[64];
@@ -125,9 +122,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ unsigned short sAM[kMaskWin][kMaxVars / kBlockBits];  // attempted bits per (sweep, block)
   __shared__ unsigned short sAL[kMaskWin * (kMaxVars / kBlockBits)];  // active (sweep, block), stream order
   __shared__ int sNA;                                                  // their number
-  // late field chunks of each (block, streaming wave): first (offset in the
-  // late part of the list) and count; waves holding pair tiles take fewer
-  __shared__ __attribute__((aligned(4))) unsigned short sLF[kMaxVars / kBlockBits][NS][2];
+  // schedule header of each (block, streaming wave): first slot word, then
+  // (early slots << 16) | slots
+  __shared__ uint2 sHdr[kMaxVars / kBlockBits][NS];
   __shared__ double strace[kSweepWin];  // per-sweep tile minima, written back after the launch's sweeps
 
   build_luts(&L);
@@ -193,34 +190,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
       __syncthreads();
     }
-    // balanced late parts: quota Q per wave of late field chunks plus pair
-    // chunks; wave v takes max(0, Q - its pair chunks) late field chunks in
-    // order, the last wave whatever remains
-    for (int e = threadIdx.x; e < NB * NS; e += blockDim.x) {
-      const int q = e / NS, v = e - q * NS;
-      const BlockMeta& m = sBM[q];
-      const int ne = masked ? 0 : (int)m.nearly;
-      const int nl = (int)m.nchunks[0] - ne;
-      auto pairs_of = [&](int wv) {
-        int c = 0;
-        for (int t = wv; t < (int)m.npt; t += NS) c += (int)m.nchunks[1 + t];
-        return c;
-      };
-      int tot = nl;
-      for (int t = 0; t < (int)m.npt; ++t) tot += (int)m.nchunks[1 + t];
-      const int quota = (tot + NS - 1) / NS;
-      int off = 0;
-      for (int wv = 0; wv < v; ++wv) {
-        const int f = quota - pairs_of(wv);
-        off += f > 0 ? f : 0;
-      }
-      off = off < nl ? off : nl;
-      int f = quota - pairs_of(v);
-      f = f > 0 ? f : 0;
-      f = v == NS - 1 ? nl - off : (f < nl - off ? f : nl - off);
-      sLF[q][v][0] = (unsigned short)off;
-      sLF[q][v][1] = (unsigned short)f;
-    }
+    for (int e = threadIdx.x; e < NB * NS; e += blockDim.x)
+      sHdr[e / NS][e % NS] = uint2{gld(I.sched_hdr + 2 * e), gld(I.sched_hdr + 2 * e + 1)};
     __syncthreads();
     const int nact = masked ? __builtin_amdgcn_readfirstlane(sNA) : (p.s_end - p.s_begin) * NB;
     // (sweep, block) of active ordinal o, given those of o - 1
@@ -237,17 +208,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     int cs = p.s_begin, cq = 0;  // sweep and block of active ordinal 0
     if (masked && nact > 0) step_block(0, cs, cq);
 
-    // the order-3 table of block (s, q) and the uniforms -log(u) of its
-    // 16 x 16 decisions into buffer bf, by one wave; returns once they are in LDS
-    auto stage = [&](int s, int q, int bf) {
+    // Staging of block (s, q) into buffer bf, by one wave: its order-3
+    // table, straight from global memory into LDS (no registers; in LDS once
+    // the wave's loads have drained), and the uniforms -log(u) of its 16 x 16
+    // decisions.
+    auto stage_table = [&](int q, int bf) {
       const int lane = lane_id();
-      const int rep = lane >> 2, sub = lane & 3;
-      // the table goes straight from global memory into LDS (no registers)
       const float* src = I.triples + (size_t)q * 4096;
 #pragma unroll
       for (int e = 0; e < 16; ++e)
         __builtin_amdgcn_global_load_lds(src + 256 * e + 4 * lane,
                                          (__attribute__((address_space(3))) void*)(&sC[bf][256 * e]), 16, 0, 0);
+    };
+    auto stage_uniforms = [&](int s, int q, int bf) {
+      const int lane = lane_id();
+      const int rep = lane >> 2, sub = lane & 3;
       // lane (rep, grp) draws the four words of bits 16q + 4 grp .. +3
       U64x4 o = philox((unsigned long long)(r0 + rep), (unsigned long long)s, (unsigned long long)(4 * q + sub),
                        0ull, p.seed, I.inst_id);
@@ -256,8 +231,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         const double u = (double)(o.w[e] >> 11) * 0x1.0p-53;
         sL[bf][rep][4 * sub + e] = u > 0.0 ? -log(u) : INFINITY;
       }
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the table is in LDS
     };
+    auto drain = []() { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
 
     // Every role passes two work-group barriers per active block: A when the
     // block's fields and couplings are in LDS, B when its decisions are.  The
@@ -299,7 +274,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
             masked ? __builtin_amdgcn_readfirstlane((unsigned)sAM[cs - p.s_begin][q]) & full : full;
         const int bf = STAGER ? (co & 1) : 0;
         // while the streaming waves compute the block's fields: its table and uniforms
-        if (!STAGER) stage(cs, q, 0);
+        if (!STAGER) {
+          stage_table(q, 0);
+          stage_uniforms(cs, q, 0);
+          drain();
+        }
         const double beta = gld(p.beta + (cs - p.s_first));
         lds_barrier();  // A
         // ---- sixteen sequential decisions, sub-lane s holding bits s, s+4, s+8, s+12
@@ -336,6 +315,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           if (!((amask >> c) & 1u)) continue;  // not attempted (or past the last variable)
+          // the order-3 rows w_{c a b} this step may need (b = c+1 .. 4i+2), read
+          // as float4 before the decision so that their latency overlaps it
+          f4 rw[4][4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (4 * i + 3 > c && k >= ((c + 1) >> 2) && k <= i)
+                rw[i][k] = *reinterpret_cast<const f4*>(&sC[bf][(c * 16 + sub + 4 * i) * 16 + 4 * k]);
           const int ic = c >> 2;
           const unsigned xc = (xb >> c) & 1u;
           const float gc = gq[ic];
@@ -353,12 +341,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               if (4 * i + 3 > c) {
-                const int a = sub + 4 * i;
                 gq[i] = fmaf(dl, hc[i][c], gq[i]);
-                const float* row = &sC[bf][(c * 16 + a) * 16];
 #pragma unroll
                 for (int b = 0; b < 16; ++b)
-                  if (b > c && b < 4 * i + 3) hc[i][b] = fmaf(dl, row[b], hc[i][b]);
+                  if (b > c && b < 4 * i + 3) hc[i][b] = fmaf(dl, rw[i][b >> 2][b & 3], hc[i][b]);
               }
             }
           }
@@ -387,54 +373,51 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
       __builtin_amdgcn_s_setprio(0);
     } else if (STAGER && w == 1) {
-      // ================= staging wave: block o + 1 while block o is decided
-      int ss = cs, sq = cq;
-      if (nact > 0) stage(ss, sq, 0);
+      // ================= staging wave.  Blocks 0 and 1 before the loop; then
+      // the table of block o + 2 goes out right after B(o), when its buffer
+      // is free, and the uniforms of block o + 1 are computed while block o
+      // is decided; the table loads have drained by B(o).
+      int s1 = cs, q1 = cq;  // block o + 1 (block 0 before the loop)
+      if (nact > 0) {
+        stage_table(cq, 0);
+        stage_uniforms(cs, cq, 0);
+      }
+      if (nact > 1) {
+        step_block(1, s1, q1);
+        stage_table(q1, 1);
+        stage_uniforms(s1, q1, 1);
+      }
+      drain();
+      int s2 = s1, q2 = q1;  // the last block whose table went out
       for (int co = 0; co < nact; ++co) {
         lds_barrier();  // A
-        if (co + 1 < nact) {
-          step_block(co + 1, ss, sq);
-          stage(ss, sq, (co + 1) & 1);
-        }
+        if (co >= 1 && co + 1 < nact) stage_uniforms(s1, q1, (co + 1) & 1);
+        drain();
         lds_barrier();  // B
+        if (co + 2 < nact) {
+          step_block(co + 2, s2, q2);
+          stage_table(q2, co & 1);
+          s1 = s2;
+          q1 = q2;
+        }
       }
     } else {
       // ================= streaming waves: the block's fields and couplings
       const int ws = w - W0;
       const int lane = lane_id();
       const int g = lane >> 4, j = lane & 15;
-      // producer: straight-line, scalar; block changes every `padded` slots
-      BProd<HT> pr{};
+      // producer: the wave's slot words of the current block, one round (D
+      // words, one scalar load) at a time; a block's slots are whole rounds
+      BProd pr{};
       auto setup_block = [&]() {
-        const BlockMeta& m = sBM[pr.q];
-        const int npt = __builtin_amdgcn_readfirstlane((int)m.npt);
-        // with attempt masks the block before is not known when packing: no early part
-        const int ne = masked ? 0 : __builtin_amdgcn_readfirstlane((int)m.nearly);
-        // early chunks in turn (chunk g0e + k NS), late ones a contiguous range
-        pr.ce = ne > ws ? (ne - ws + NS - 1) / NS : 0;
-        const unsigned lf = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const unsigned*>(&sLF[pr.q][ws][0]));
-        pr.cl = (int)(lf >> 16);
-        const unsigned c0 = __builtin_amdgcn_readfirstlane(m.chunk0[0]);
-        pr.g0e = c0 + (unsigned)ws;
-        pr.g0l = c0 + (unsigned)ne + (lf & 0xFFFFu);
-        int tot = 0;
-#pragma unroll
-        for (int mm = 0; mm < HT; ++mm) {
-          const int t = ws + mm * NS;
-          const bool ok = t < npt;
-          pr.hs[mm] = tot;
-          pr.hn[mm] = ok ? __builtin_amdgcn_readfirstlane((int)m.nchunks[1 + (ok ? t : 0)]) : 0;
-          pr.hc0[mm] = ok ? __builtin_amdgcn_readfirstlane(m.chunk0[1 + (ok ? t : 0)]) : 0u;
-          tot += pr.hn[mm];
-        }
-        tot += pr.cl;
-        pr.pe = (pr.ce + D - 1) / D * D;
-        const int pl = (tot + D - 1) / D * D;
-        pr.padded = pr.pe + (pr.pe + pl == 0 ? D : pl);
+        const uint2 h = sHdr[pr.q][ws];
+        pr.off = __builtin_amdgcn_readfirstlane(h.x);
+        const unsigned cnt = __builtin_amdgcn_readfirstlane(h.y);
+        pr.pe = (int)(cnt >> 16);
+        pr.padded = (int)(cnt & 0xFFFFu);
         pr.k = 0;
       };
-      // the producer enters its next active block; its slot counts are whole
-      // rounds of D, so this happens only between rounds
+      // the producer enters its next active block (only between rounds)
       auto advance = [&]() {
         if (pr.k == pr.padded) {
           ++pr.ord;
@@ -445,40 +428,29 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
           pr.k = 0;
         }
       };
-      auto issue = [&](BSlot<P>& sl) {
-        const int k = pr.k;
-        unsigned c = 0;
-        int kind = 2, tgt = 0;
-        const int part = k < pr.pe ? 0 : 1;
-        if (k < pr.pe) {  // early field chunks; the last closes the list when no late ones follow
-          if (k < pr.ce) {
-            c = pr.g0e + (unsigned)(k * NS);
-            kind = (k == pr.ce - 1 && pr.cl == 0) ? 1 : 0;
-          }
-        } else if (k - pr.pe < pr.cl) {
-          const int kl = k - pr.pe;
-          c = pr.g0l + (unsigned)kl;
-          kind = kl == pr.cl - 1 ? 1 : 0;
-        } else {
-          const int kk = k - pr.pe - pr.cl;
+      unsigned wd[D];  // slot words of the round being issued
+      auto fetch = [&]() {
+        if (pr.ord < nact) {
+          typedef const __attribute__((address_space(4))) u4* ConstU4;
+          const ConstU4 sp = (ConstU4)(I.sched + pr.off + pr.k);
+          const u4 a = sp[0], b = sp[1];
 #pragma unroll
-          for (int mm = 0; mm < HT; ++mm)
-            if (kk >= pr.hs[mm] && kk < pr.hs[mm] + pr.hn[mm]) {
-              c = pr.hc0[mm] + (unsigned)(kk - pr.hs[mm]);
-              kind = kk == pr.hs[mm] + pr.hn[mm] - 1 ? 1 : 0;
-              tgt = 1 + ws + mm * NS;
-            }
+          for (int d = 0; d < 4; ++d) {
+            wd[d] = a[d];
+            wd[4 + d] = b[d];
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < D; ++d) wd[d] = kSlotEnd;  // past the last block
         }
-        pr.k = k + 1;
-        if (pr.ord >= nact) {  // past the last block
-          kind = 3;
-          c = 0;
-        }
-        sl.kind = __builtin_amdgcn_readfirstlane(kind);
-        sl.tgt = __builtin_amdgcn_readfirstlane(tgt);
-        sl.ord = __builtin_amdgcn_readfirstlane(2 * pr.ord + part);  // (block, part)
-        unsigned tix = kind <= 1 ? c + 1u : 0u;
-        tix = tix < I.n_tiles ? tix : 0u;  // never outside the tile buffer
+      };
+      auto issue = [&](BSlot<P>& sl, unsigned word) {
+        const unsigned tix = word & 0xFFFFFu;  // tile (chunk + 1; 0 = the zero tile)
+        sl.kind = (int)((word >> 20) & 3u);
+        sl.tgt = (int)(word >> 22);
+        sl.ord = 2 * pr.ord + (pr.k >= pr.pe ? 1 : 0);  // (block, part)
+        ++pr.k;
+        const unsigned c = tix ? tix - 1u : 0u;
         load_tile<P>(sl.b, I.tiles + (size_t)tix * TB, lane);
         sl.d = gld(reinterpret_cast<const unsigned*>(I.runs + (size_t)c * RPC + g));
       };
@@ -488,8 +460,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       pr.q = cq;
       if (nact > 0) setup_block();
       BSlot<P> ring[D];
+      fetch();
 #pragma unroll
-      for (int d = 0; d < D; ++d) issue(ring[d]);
+      for (int d = 0; d < D; ++d) issue(ring[d], wd[d]);
 
       AccT<P> acc;
       acc_zero<P>(acc);
@@ -498,6 +471,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       // the matrix-core work of slot d, so its LDS reads overlap that work
       auto round = [&](float* myG) {
         advance();
+        fetch();
         auto gen = [&](const BSlot<P>& sl) {
           // every slot's registers are consumed on every path (padding slots
           // multiply a zero operand), so the counted waits stay exact
@@ -530,7 +504,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
             }
             acc_zero<P>(acc);
           }
-          issue(sl);
+          issue(sl, wd[d]);
         }
       };
       for (int co = 0; co < nact; ++co) {

@@ -83,6 +83,25 @@ struct BlockMeta {
   uint32_t nearly;                // leading chunks of the field list that read no bit of the
                                   // block before it in a sweep (block q-1, or the last for q = 0)
 };
+// Blocked annealer work schedule.  For a work-group of nw waves (wave 0
+// decides; with 16 waves wave 1 stages; the other NS stream) each block's
+// chunks are dealt to the NS streaming waves as whole rounds of kBlockRing
+// slots: first the early part (field chunks that read no bit of the block
+// before), then the late part (the other field chunks, then the wave's pair
+// tiles).  One 32-bit word per slot: tile index (chunk + 1, 0 = the zero
+// tile) in bits 0..19, kind in bits 20..21 (0 chunk, 1 chunk that closes
+// its list, 2 padding, 3 past the last block), target list in bits 22..25
+// (0 fields, 1 + t pair tile t).  Header per (block, wave): word offset of
+// its slots, then (early slots << 16) | slots.
+constexpr int kBlockRing = 8;
+constexpr uint32_t kSlotPad = 2u << 20, kSlotEnd = 3u << 20;
+inline int block_streamers(int nw) { return nw - 1 - (nw == 16 ? 1 : 0); }
+struct BlockSchedule {
+  uint32_t* d_words = nullptr;
+  uint32_t* d_hdr = nullptr;  // [nblocks][NS][2]
+  ~BlockSchedule();
+};
+
 // pair (a, b), a < b < 16, of a block -> its column among the 120 pair columns
 __host__ __device__ inline int pair_col(int a, int b) { return b * (b - 1) / 2 + a; }
 
@@ -99,6 +118,8 @@ struct Packed {
   BlockMeta* d_blocks = nullptr;  // blocks mode only, [nblocks]
   float* d_triples = nullptr;     // blocks mode only, [nblocks][16][16][16] w_{abc} at [c][a][b]
   int nblocks = 0;
+  std::vector<BlockMeta> h_blocks;  // blocks mode only
+  std::map<int, std::unique_ptr<BlockSchedule>> sched;  // blocks mode: key = nw * 2 + masked
   std::vector<ChunkMeta> h_chunks;
   size_t bytes = 0;
   ~Packed();
@@ -164,6 +185,8 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
 
 // pack.cpp -- build (once) the packed layout; returns a status code
 int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err);
+// the blocked annealer's schedule for nw-wave work-groups (built on first use)
+int get_block_schedule(Tensor* t, Packed* pk, int nw, bool masked, const BlockSchedule** out, std::string* err);
 int get_terms(Tensor* t, TermsDev** out, std::string* err);
 int get_row_norms(Tensor* t, const double** out, std::string* err);
 
@@ -231,6 +254,8 @@ struct AnnealInstDev {       // per-instance view of the annealing kernel
   unsigned pad2;
   const BlockMeta* blocks;     // blocked layout: [nblocks]
   const float* triples;        // blocked layout: [nblocks][16][16][16]
+  const uint32_t* sched;       // blocked layout: slot words of the launch's group width
+  const uint32_t* sched_hdr;   // and their headers [nblocks][NS][2]
   int nblocks;
   int pad3;
 };

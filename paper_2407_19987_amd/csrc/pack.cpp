@@ -44,6 +44,10 @@ Packed::~Packed() {
   if (d_blocks) (void)hipFree(d_blocks);
   if (d_triples) (void)hipFree(d_triples);
 }
+BlockSchedule::~BlockSchedule() {
+  if (d_words) (void)hipFree(d_words);
+  if (d_hdr) (void)hipFree(d_hdr);
+}
 TermsDev::~TermsDev() {
   if (d_rec) (void)hipFree(d_rec);
 }
@@ -458,6 +462,7 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
     }
     pk->nchunks = (int)po.chunks.size();
     pk->nblocks = nb;
+    pk->h_blocks = bm;
     st = upload(bm, &pk->d_blocks, &pk->bytes, err);
     if (st) return st;
     st = upload(tri, &pk->d_triples, &pk->bytes, err);
@@ -524,6 +529,91 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
   if (st) return st;
   *out = pk.get();
   t->packed.emplace(key, std::move(pk));
+  return HOBO_OK;
+}
+
+int get_block_schedule(Tensor* t, Packed* pk, int nw, bool masked, const BlockSchedule** out, std::string* err) {
+  std::lock_guard<std::mutex> lock(t->mu);
+  const int key = nw * 2 + (masked ? 1 : 0);
+  auto it = pk->sched.find(key);
+  if (it != pk->sched.end()) {
+    *out = it->second.get();
+    return HOBO_OK;
+  }
+  const int ns = block_streamers(nw);
+  if (ns < 1 || pk->h_blocks.empty()) {
+    *err = "no blocked layout for this work-group width";
+    return HOBO_ERR_INVALID_ARG;
+  }
+  if ((int64_t)pk->nchunks + 1 >= (int64_t)1 << 20) {
+    *err = "blocked schedule: more chunks than a slot word holds";
+    return HOBO_ERR_RANGE;
+  }
+  constexpr int D = kBlockRing;
+  std::vector<uint32_t> words, hdr;
+  auto pad_to_round = [&](size_t from) {
+    while ((words.size() - from) % D) words.push_back(kSlotPad);
+  };
+  for (const BlockMeta& m : pk->h_blocks) {
+    // early part: the leading `nearly` field chunks in equal contiguous
+    // ranges; late part: a quota Q of late field chunks plus pair chunks per
+    // wave (pair tile t belongs to wave t mod NS), the late field chunks in
+    // order, the last wave taking whatever remains
+    const int ne = masked ? 0 : (int)m.nearly;
+    const int nl = (int)m.nchunks[0] - ne;
+    const int npt = (int)m.npt;
+    auto pairs_of = [&](int v) {
+      int c = 0;
+      for (int tt = v; tt < npt; tt += ns) c += (int)m.nchunks[1 + tt];
+      return c;
+    };
+    int tot = nl;
+    for (int tt = 0; tt < npt; ++tt) tot += (int)m.nchunks[1 + tt];
+    const int quota = (tot + ns - 1) / ns;
+    int loff = 0;
+    for (int v = 0; v < ns; ++v) {
+      const int e0 = ne * v / ns, e1 = ne * (v + 1) / ns;
+      int lc = std::max(0, quota - pairs_of(v));
+      lc = v == ns - 1 ? nl - loff : std::min(lc, nl - loff);
+      const uint32_t c0 = m.chunk0[0];
+      // the wave's last field chunk closes its field list
+      const int64_t last = lc > 0 ? (int64_t)c0 + ne + loff + lc - 1 : (e1 > e0 ? (int64_t)c0 + e1 - 1 : -1);
+      auto chunk_word = [&](uint32_t c, bool close, int tgt) {
+        return (c + 1u) | ((close ? 1u : 0u) << 20) | ((uint32_t)tgt << 22);
+      };
+      const size_t base = words.size();
+      for (int c = e0; c < e1; ++c) words.push_back(chunk_word(c0 + c, (int64_t)(c0 + c) == last, 0));
+      pad_to_round(base);
+      const int pe = (int)(words.size() - base);
+      for (int c = 0; c < lc; ++c) {
+        const uint32_t cc = c0 + (uint32_t)(ne + loff + c);
+        words.push_back(chunk_word(cc, (int64_t)cc == last, 0));
+      }
+      for (int tt = v; tt < npt; tt += ns)
+        for (uint32_t c = 0; c < m.nchunks[1 + tt]; ++c)
+          words.push_back(chunk_word(m.chunk0[1 + tt] + c, c + 1 == m.nchunks[1 + tt], 1 + tt));
+      pad_to_round(base);
+      if (words.size() == base)
+        for (int d = 0; d < D; ++d) words.push_back(kSlotPad);
+      hdr.push_back((uint32_t)base);
+      hdr.push_back(((uint32_t)pe << 16) | (uint32_t)(words.size() - base));
+      loff += lc;
+    }
+  }
+  for (uint32_t w : words)
+    if ((w & 0xFFFFFu) >= (uint32_t)pk->ntiles) {
+      *err = "blocked schedule: tile index out of range";
+      return HOBO_ERR_RANGE;
+    }
+  std::unique_ptr<BlockSchedule> bs(new BlockSchedule());
+  size_t bytes = 0;
+  int st = upload(words, &bs->d_words, &bytes, err);
+  if (st) return st;
+  st = upload(hdr, &bs->d_hdr, &bytes, err);
+  if (st) return st;
+  pk->bytes += bytes;
+  *out = bs.get();
+  pk->sched.emplace(key, std::move(bs));
   return HOBO_OK;
 }
 
