@@ -556,7 +556,22 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       learn_bytes += align((size_t)replicas[j] * n * (tensors[j]->t.integer ? 8 : 4));
       learn_bytes += align((size_t)((replicas[j] + 15) / 16) * P.refresh * n);
     }
-  size_t total = align(off_learn + learn_bytes);
+  // the blocked kernel's uniforms -log(u): one launch window at a time,
+  // 2 KB per (16 replicas, sweep, block); the window is cut to keep them
+  // within 1 GiB
+  size_t unif_per_sweep = 0;
+  for (int j = 0; j < n_instances; ++j)
+    if (blocked[(size_t)j])
+      unif_per_sweep += (size_t)((replicas[j] + 15) / 16) * (size_t)pks[(size_t)j]->nblocks * 2048;
+  const int win_max = P.proposal != HOBO_PROPOSAL_METROPOLIS ? hobo::anneal_mask_window() : hobo::anneal_sweep_window();
+  int unif_sweeps = 0;
+  if (unif_per_sweep > 0) {
+    const size_t cap = (size_t)1 << 30;
+    unif_sweeps = (int)std::min<size_t>((size_t)std::min(win_max, std::max(S, 1)),
+                                        std::max<size_t>(1, cap / unif_per_sweep));
+  }
+  size_t off_unif = align(off_learn + learn_bytes);
+  size_t total = align(off_unif + unif_per_sweep * (size_t)unif_sweeps);
   std::vector<hobo::Packed*> fpks((size_t)n_instances, nullptr);
   std::vector<const double*> rns((size_t)n_instances, nullptr);
   if (learned)
@@ -656,7 +671,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     std::vector<hobo::InstSmall> small((size_t)n_instances);
     std::vector<std::vector<hobo::AnnealItem>> items_of((size_t)n_instances);
     int64_t xoff = 0, roff = 0, toff = 0, att_off = 0;
-    size_t term_off = 0, learn_off = 0;
+    size_t term_off = 0, learn_off = 0, unif_off = 0;
     int max_ct = 1, max_nw = 1;
     ne.beta = beta;
     if (learned) {
@@ -681,6 +696,10 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       d.blocks = pk->d_blocks;
       d.triples = pk->d_triples;
       d.nblocks = pk->nblocks;
+      if (blocked[(size_t)j]) {
+        d.unif = reinterpret_cast<double*>(wb + off_unif + unif_off);
+        unif_off += (size_t)nt * (size_t)pk->nblocks * 2048 * (size_t)unif_sweeps;
+      }
       d.x = reinterpret_cast<unsigned long long*>(x_inout + xoff);
       d.best_x = reinterpret_cast<unsigned long long*>(best_x_out + xoff);
       d.e_track = reinterpret_cast<double*>(wb + off_e) + roff;
@@ -808,6 +827,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     ne.tb.max_W = max_W;
     ne.tb.max_groups = max_groups;
     ne.tb.d_ones = reinterpret_cast<const unsigned char*>(wb + off_ones);
+    ne.tb.unif_sweeps = unif_sweeps;
     hipError_t e = hipMemcpy(ne.tb.d_inst, inst.data(), inst.size() * sizeof(inst[0]), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(ne.tb.d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice);

@@ -39,6 +39,7 @@
 namespace hobo {
 
 constexpr int kRing = 8;       // chunks in flight per wave
+constexpr int kBufferFlags = 0x00020000;  // buffer resource word 3: raw byte-addressed data
 constexpr int kMaskWin = 64;   // sweeps per launch when attempt masks are used
 constexpr int kSweepWin = 256; // sweeps per launch otherwise (their trace waits in LDS)
 
@@ -68,6 +69,13 @@ __device__ inline int quad_bcast(int v, int o) {
     case 2: return dpp_i<0xAA>(v);
     default: return dpp_i<0xFF>(v);
   }
+}
+
+// A pointer every lane holds, in scalar registers.
+template <class T> __device__ inline void* uniform_ptr(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v), hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
 }
 
 // Lane id read from the hardware counter where it is needed (the asm is not
@@ -117,7 +125,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ __attribute__((aligned(16))) float sH[16][16][16];  // pair couplings [rep][a][b], b < a
   __shared__ unsigned short sPC[128];  // pair column -> (a << 8) | b (unused columns -> 0)
   __shared__ __attribute__((aligned(16))) float sC[NBUF][4096];  // order-3 table of the block [c][a][b]
-  __shared__ double sL[NBUF][16][17];       // -log(u) [rep][bit]
+  __shared__ __attribute__((aligned(16))) double sL[NBUF][16][16];  // -log(u) [rep][bit]
   __shared__ BlockMeta sBM[kMaxVars / kBlockBits];
   __shared__ unsigned short sAM[kMaskWin][kMaxVars / kBlockBits];  // attempted bits per (sweep, block)
   __shared__ unsigned short sAL[kMaskWin * (kMaxVars / kBlockBits)];  // active (sweep, block), stream order
@@ -220,17 +228,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         __builtin_amdgcn_global_load_lds(src + 256 * e + 4 * lane,
                                          (__attribute__((address_space(3))) void*)(&sC[bf][256 * e]), 16, 0, 0);
     };
+    // the uniforms come from the window's buffer (anneal_uniforms_kernel), 2 KB
     auto stage_uniforms = [&](int s, int q, int bf) {
       const int lane = lane_id();
-      const int rep = lane >> 2, sub = lane & 3;
-      // lane (rep, grp) draws the four words of bits 16q + 4 grp .. +3
-      U64x4 o = philox((unsigned long long)(r0 + rep), (unsigned long long)s, (unsigned long long)(4 * q + sub),
-                       0ull, p.seed, I.inst_id);
+      const double* src = I.unif + ((size_t)item.tile16 * p.unif_sweeps + (s - p.s_begin)) * ((size_t)NB * 256) +
+                          (size_t)q * 256;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double u = (double)(o.w[e] >> 11) * 0x1.0p-53;
-        sL[bf][rep][4 * sub + e] = u > 0.0 ? -log(u) : INFINITY;
-      }
+      for (int e = 0; e < 2; ++e)
+        __builtin_amdgcn_global_load_lds(src + 128 * e + 2 * lane,
+                                         (__attribute__((address_space(3))) void*)(&sL[bf][0][0] + 128 * e), 16, 0,
+                                         0);
     };
     auto drain = []() { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
 
@@ -374,31 +381,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       __builtin_amdgcn_s_setprio(0);
     } else if (STAGER && w == 1) {
       // ================= staging wave.  Blocks 0 and 1 before the loop; then
-      // the table of block o + 2 goes out right after B(o), when its buffer
-      // is free, and the uniforms of block o + 1 are computed while block o
-      // is decided; the table loads have drained by B(o).
-      int s1 = cs, q1 = cq;  // block o + 1 (block 0 before the loop)
+      // block o + 2 goes out right after B(o), when its buffers are free, and
+      // has landed by B(o + 1): a whole block's time for the loads.
+      int s2 = cs, q2 = cq;  // the last block sent
       if (nact > 0) {
         stage_table(cq, 0);
         stage_uniforms(cs, cq, 0);
       }
       if (nact > 1) {
-        step_block(1, s1, q1);
-        stage_table(q1, 1);
-        stage_uniforms(s1, q1, 1);
+        step_block(1, s2, q2);
+        stage_table(q2, 1);
+        stage_uniforms(s2, q2, 1);
       }
       drain();
-      int s2 = s1, q2 = q1;  // the last block whose table went out
       for (int co = 0; co < nact; ++co) {
         lds_barrier();  // A
-        if (co >= 1 && co + 1 < nact) stage_uniforms(s1, q1, (co + 1) & 1);
         drain();
         lds_barrier();  // B
         if (co + 2 < nact) {
           step_block(co + 2, s2, q2);
           stage_table(q2, co & 1);
-          s1 = s2;
-          q1 = q2;
+          stage_uniforms(s2, q2, co & 1);
         }
       }
     } else {
@@ -444,15 +447,31 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
           for (int d = 0; d < D; ++d) wd[d] = kSlotEnd;  // past the last block
         }
       };
+      // tiles and run words through buffer resources: the slot's offset is
+      // a scalar, the lane's part a constant register (reads past the end
+      // return zero)
+      const __amdgpu_buffer_rsrc_t tiles_rs = __builtin_amdgcn_make_buffer_rsrc(
+          uniform_ptr(I.tiles), 0, (int)__builtin_amdgcn_readfirstlane(I.n_tiles * (unsigned)TB), kBufferFlags);
+      const __amdgpu_buffer_rsrc_t runs_rs = __builtin_amdgcn_make_buffer_rsrc(
+          uniform_ptr(I.runs), 0, __builtin_amdgcn_readfirstlane(I.n_chunks * RPC * 8), kBufferFlags);
       auto issue = [&](BSlot<P>& sl, unsigned word) {
         const unsigned tix = word & 0xFFFFFu;  // tile (chunk + 1; 0 = the zero tile)
         sl.kind = (int)((word >> 20) & 3u);
         sl.tgt = (int)(word >> 22);
         sl.ord = 2 * pr.ord + (pr.k >= pr.pe ? 1 : 0);  // (block, part)
         ++pr.k;
-        const unsigned c = tix ? tix - 1u : 0u;
-        load_tile<P>(sl.b, I.tiles + (size_t)tix * TB, lane);
-        sl.d = gld(reinterpret_cast<const unsigned*>(I.runs + (size_t)c * RPC + g));
+        const int toff = __builtin_amdgcn_readfirstlane((int)(tix * (unsigned)TB));
+        const int roff = __builtin_amdgcn_readfirstlane((int)((tix ? tix - 1u : 0u) * (unsigned)(RPC * 8)));
+        if constexpr (P == P_FP32) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            sl.b.v[q] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(tiles_rs, lane * 32 + 16 * q, toff, 0));
+        } else {
+#pragma unroll
+          for (int q = 0; q < PT<P>::NLD; ++q)
+            sl.b.v[q] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(tiles_rs, q * 1024 + lane * 16, toff, 0));
+        }
+        sl.d = __builtin_amdgcn_raw_buffer_load_b32(runs_rs, g * 8, roff, 0);
       };
 
       pr.ord = 0;
@@ -544,6 +563,42 @@ int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipS
   HOBO_AB(P_BF16X3, 2) HOBO_AB(P_BF16X3, 4) HOBO_AB(P_BF16X3, 8) HOBO_AB(P_BF16X3, 16)
 #undef HOBO_AB
   return -1;
+}
+
+// -log(u) of every (replica, sweep, bit) of a blocked launch window, one
+// work-group per (sweep, 16-replica item): thread (q, rep, grp) draws the
+// four Philox words of bits 16q + 4 grp .. +3 (counter: replica, sweep,
+// 4q + grp, tag 0) and stores them at [item][sweep][q][rep][bit].
+__global__ __launch_bounds__(256) void anneal_uniforms_kernel(AnnealParams p) {
+  const int sr = blockIdx.y;
+  const int s = p.s_begin + sr;
+  for (int it = blockIdx.x; it < p.n_items; it += gridDim.x) {
+    const AnnealItem item = p.items[it];
+    const AnnealInstDev* I = p.insts + item.inst;
+    const int NB = I->nblocks;
+    const unsigned long long inst_id = I->inst_id;
+    double* dst = I->unif + ((size_t)item.tile16 * p.unif_sweeps + sr) * ((size_t)NB * 256);
+    const long long r0 = (long long)item.tile16 * 16;
+    for (int u = threadIdx.x; u < NB * 64; u += blockDim.x) {
+      const int q = u >> 6, rep = (u >> 2) & 15, grp = u & 3;
+      const U64x4 o = philox((unsigned long long)(r0 + rep), (unsigned long long)s, (unsigned long long)(4 * q + grp),
+                             0ull, p.seed, inst_id);
+      double v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double uu = (double)(o.w[e] >> 11) * 0x1.0p-53;
+        v[e] = uu > 0.0 ? -log(uu) : INFINITY;
+      }
+      double* d = dst + q * 256 + rep * 16 + 4 * grp;
+      *reinterpret_cast<d2*>(d) = d2{v[0], v[1]};
+      *reinterpret_cast<d2*>(d + 2) = d2{v[2], v[3]};
+    }
+  }
+}
+
+void launch_anneal_uniforms(const AnnealParams& ap, hipStream_t st) {
+  const unsigned gx = (unsigned)(ap.n_items < 4096 ? ap.n_items : 4096);
+  hipLaunchKernelGGL(anneal_uniforms_kernel, dim3(gx, (unsigned)(ap.s_end - ap.s_begin)), dim3(256), 0, st, ap);
 }
 
 int anneal_mask_window() { return kMaskWin; }

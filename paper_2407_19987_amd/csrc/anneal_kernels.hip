@@ -409,8 +409,7 @@ void anneal_shape(int T, int cs_req, int* ctw, int* cs) {
 }
 
 int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipStream_t st);
-int anneal_mask_window();
-int anneal_sweep_window();
+void launch_anneal_uniforms(const AnnealParams& ap, hipStream_t st);
 
 // The annealing sequence of one launch plan, in three parts: random start
 // states and start energies (FP64 / int64 term sums); the sweeps (blocked
@@ -454,12 +453,16 @@ int enqueue_anneal_sweeps(const AnnealTables& tb, const AnnealPlan& pl, int s_be
     ap.items = tb.d_items + pl.item0;
     ap.n_items = pl.n_blk;
     const int nblk = pl.n_blk < 2048 ? pl.n_blk : 2048;
-    const int win = pl.masked ? anneal_mask_window() : anneal_sweep_window();
+    const int win0 = pl.masked ? anneal_mask_window() : anneal_sweep_window();
+    const int win = tb.unif_sweeps > 0 && tb.unif_sweeps < win0 ? tb.unif_sweeps : win0;
+    ap.unif_sweeps = tb.unif_sweeps;
     int s0 = s_begin;
     do {  // at least one launch: with no sweeps it writes the start states back as the best ones
       ap.s_begin = s0;
       ap.s_end = s_end - s0 < win ? s_end : s0 + win;
       ap.cont = (cont || s0 > s_begin) ? 1 : 0;
+      // the window's Metropolis uniforms first (a kernel of their own)
+      if (ap.s_end > ap.s_begin) launch_anneal_uniforms(ap, st);
       if (launch_anneal_block(ap, pl.prec, pl.nw_blk, nblk, st) != 0) {
         *err = "no blocked annealer kernel for this precision / width";
         return HOBO_ERR_UNSUPPORTED;

@@ -30,6 +30,7 @@ typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 // Global-memory loads through the global address space: generic (flat)
 // loads would also count against the LDS wait counter, so every LDS access
@@ -346,6 +347,7 @@ struct AnnealParams {
   const double* beta;         // [S] inverse temperatures
   unsigned long long seed;
   const unsigned char* ones;  // a device byte equal to 1 (attempt flag without masks)
+  int unif_sweeps;            // blocked kernel: sweep stride of the uniform buffers
 };
 
 inline int hip_fail(hipError_t e, std::string* err, const char* what) {

@@ -256,6 +256,8 @@ struct AnnealInstDev {       // per-instance view of the annealing kernel
   const float* triples;        // blocked layout: [nblocks][16][16][16]
   const uint32_t* sched;       // blocked layout: slot words of the launch's group width
   const uint32_t* sched_hdr;   // and their headers [nblocks][NS][2]
+  double* unif;                // blocked layout: -log(u) of a launch window,
+                               // [ntiles16][window sweeps][nblocks][16 replicas][16 bits]
   int nblocks;
   int pad3;
 };
@@ -292,10 +294,14 @@ struct AnnealTables {         // device tables of one anneal call
   long long max_B = 0;
   int max_W = 0;
   int max_groups = 1;         // term-loop groups of the largest instance
+  int unif_sweeps = 0;        // sweeps of one blocked launch window the uniform buffers hold
 };
 
 // (column tiles per wave, waves per work-group) of the annealer for T column tiles
 void anneal_shape(int T, int cs_req, int* ctw, int* cs);
+// sweeps per blocked-kernel launch with attempt masks / without
+int anneal_mask_window();
+int anneal_sweep_window();
 
 // launch timing (kernels: 0 = annealer, 1 = fields, 2 = energy)
 void timing_enable(int on);
