@@ -323,10 +323,7 @@ __global__ void init_random_multi(const InstSmall* in, unsigned long long seed) 
 
 // Term-loop energies of x (which = 0, written to the tracked start energy)
 // or of best_x (which = 1, written to the rescored output); grid.z = instance
-__global__ __launch_bounds__(256) void term_partial_multi(const InstSmall* in, int which) {
-  __shared__ TermRec srec[kTermStage];
-  const InstSmall I = in[blockIdx.z];
-  if ((long long)blockIdx.x * 256 >= I.B || (int)blockIdx.y * kTermGroup >= I.n_mono) return;
+__device__ inline TermJob term_job(const InstSmall& I, int which) {
   TermJob J{};
   J.rec = I.rec;
   J.n_mono = I.n_mono;
@@ -335,7 +332,19 @@ __global__ __launch_bounds__(256) void term_partial_multi(const InstSmall* in, i
   J.B = I.B;
   J.bits = which ? I.best_x : I.x;
   J.part = I.term_part;
-  term_partial(J, blockIdx.x, blockIdx.y, srec);
+  return J;
+}
+
+__global__ __launch_bounds__(256) void term_masks_multi(const InstSmall* in, int which) {
+  const InstSmall I = in[blockIdx.y];
+  if ((long long)blockIdx.x * 256 >= I.B) return;
+  term_masks(term_job(I, which), blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void term_partial_multi(const InstSmall* in, int which) {
+  const InstSmall I = in[blockIdx.z];
+  if ((long long)blockIdx.x * 256 >= I.B || (int)blockIdx.y * kTermGroup >= I.n_mono) return;
+  term_partial(term_job(I, which), blockIdx.x, blockIdx.y);
 }
 
 __global__ void term_reduce_multi(const InstSmall* in, int which) {
@@ -425,9 +434,11 @@ int enqueue_anneal_setup(const AnnealTables& tb, const AnnealPlan& pl, void* str
                        (unsigned long long)pl.seed);
   }
   const unsigned rb = (unsigned)((tb.max_B + 255) / 256);
+  hipLaunchKernelGGL(term_masks_multi, dim3(rb, ni), dim3(256), 0, st, sm, 0);
   hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, ni), dim3(256), 0, st, sm, 0);
   hipLaunchKernelGGL(term_reduce_multi, dim3(rb, ni), dim3(256), 0, st, sm, 0);
   if (pl.cont) {
+    hipLaunchKernelGGL(term_masks_multi, dim3(rb, ni), dim3(256), 0, st, sm, 2);
     hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, ni), dim3(256), 0, st, sm, 2);
     hipLaunchKernelGGL(term_reduce_multi, dim3(rb, ni), dim3(256), 0, st, sm, 2);
   }
@@ -498,6 +509,7 @@ int enqueue_anneal_finish(const AnnealTables& tb, const AnnealPlan& pl, void* st
   const InstSmall* sm = tb.d_small + pl.inst0;
   const unsigned ni = (unsigned)pl.ninst;
   const unsigned rb = (unsigned)((tb.max_B + 255) / 256);
+  hipLaunchKernelGGL(term_masks_multi, dim3(rb, ni), dim3(256), 0, st, sm, 1);
   hipLaunchKernelGGL(term_partial_multi, dim3(rb, (unsigned)tb.max_groups, ni), dim3(256), 0, st, sm, 1);
   hipLaunchKernelGGL(term_reduce_multi, dim3(rb, ni), dim3(256), 0, st, sm, 1);
   if (pl.sweeps > 0)

@@ -274,7 +274,6 @@ __device__ inline ChunkMeta unpack_meta(unsigned long long raw) {
 
 // term-loop kernels: monomials per partial sum, records staged in LDS at a time
 constexpr int kTermGroup = 4096;
-constexpr int kTermStage = 512;
 __host__ __device__ inline int term_groups(int n_mono) { return n_mono > 0 ? (n_mono + kTermGroup - 1) / kTermGroup : 1; }
 
 struct TermJob {             // one instance's term-loop energy of a batch
@@ -287,40 +286,89 @@ struct TermJob {             // one instance's term-loop energy of a batch
   const unsigned long long* bits;  // [W][B]
   void* part;                      // [term_groups][B] partial sums
 };
-__device__ inline void term_partial(const TermJob& J, int rowblock, int grp, TermRec* srec) {
-  const long long b = (long long)rowblock * 256 + threadIdx.x;
+// Bit-sliced term sums.  For each group of 64 replicas term_masks stores,
+// per variable v, the 64-bit mask whose bit r is x_{64g + r, v}.  A
+// monomial's mask over the group is the AND of its variables' masks, formed
+// once per wave from scalar loads, and lane r adds w_S when bit r is set;
+// the monomials of a group are added in list order.
+__host__ __device__ inline size_t term_mask_offset(int n_mono, long long B) {  // bytes into the workspace
+  return ((size_t)term_groups(n_mono) * (size_t)B * 8 + 255) & ~(size_t)255;
+}
+__host__ __device__ inline size_t term_mask_bytes(int n_vars, long long B) {
+  return (size_t)((B + 63) / 64) * 64 * (size_t)((n_vars + 63) / 64) * 8;
+}
+
+// work-group of 256 threads: 4 waves, one 64-replica group each
+__device__ inline void term_masks(const TermJob& J, int rowblock) {
+  const int lane = threadIdx.x & 63;
+  const long long g = (long long)rowblock * 4 + (threadIdx.x >> 6);
+  if (g * 64 >= J.B) return;
+  const long long b = g * 64 + lane;
+  unsigned long long* masks =
+      reinterpret_cast<unsigned long long*>(static_cast<char*>(J.part) + term_mask_offset(J.n_mono, J.B)) +
+      g * 64 * J.W;
+  for (int w = 0; w < J.W; ++w) {
+    const unsigned long long x = b < J.B ? gld(J.bits + (long long)w * J.B + b) : 0ull;
+    unsigned long long mine = 0;
+    for (int jb = 0; jb < 64; ++jb) {
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(((x >> jb) & 1ull) != 0);
+      if (lane == jb) mine = m;
+    }
+    masks[64 * w + lane] = mine;
+  }
+}
+
+__device__ inline void term_partial(const TermJob& J, int rowblock, int grp) {
+  const int lane = threadIdx.x & 63;
+  const long long g = (long long)rowblock * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (g * 64 >= J.B) return;
+  const long long b = g * 64 + lane;
   const int m0 = grp * kTermGroup;
   const int m1 = m0 + kTermGroup < J.n_mono ? m0 + kTermGroup : J.n_mono;
-  unsigned long long x0 = 0, x1 = 0, x2 = 0, x3 = 0;
-  if (b < J.B) {
-    x0 = gld(J.bits + b);
-    if (J.W > 1) x1 = gld(J.bits + J.B + b);
-    if (J.W > 2) x2 = gld(J.bits + 2 * J.B + b);
-    if (J.W > 3) x3 = gld(J.bits + 3 * J.B + b);
-  }
+  typedef const __attribute__((address_space(4))) unsigned long long* ConstU64;
+  typedef const __attribute__((address_space(4))) u4* ConstU4;
+  const ConstU64 masks =
+      (ConstU64)(static_cast<const char*>(J.part) + term_mask_offset(J.n_mono, J.B)) + g * 64 * J.W;
+  const ConstU4 rec = (ConstU4)J.rec;
   double sf = 0.0;
   long long si = 0;
-  for (int ms = m0; ms < m1; ms += kTermStage) {
-    const int cnt = m1 - ms < kTermStage ? m1 - ms : kTermStage;
-    __syncthreads();
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x)
-      srec[q] = __builtin_bit_cast(TermRec, gld(reinterpret_cast<const u4*>(J.rec + ms + q)));
-    __syncthreads();
-    for (int m = 0; m < cnt; ++m) {
-      const TermRec r = srec[m];
-      bool on = true;
-      for (int q = 0; q < r.len; ++q) {
-        const unsigned v = r.idx[q];
-        const unsigned long long w = v < 64 ? x0 : (v < 128 ? x1 : (v < 192 ? x2 : x3));
-        on = on && ((w >> (v & 63u)) & 1ull);
-      }
-      if (on) {
-        if (J.integer)
-          si += r.w.i;
-        else
-          sf += r.w.f;
-      }
-    }
+  // one monomial's mask over the 64 replicas: the first three variables in
+  // independent loads (unused slots repeat idx[0], so shorter monomials AND
+  // the same mask again), any further ones after
+  auto mask3 = [&](const u4& r) {
+    return masks[r[0] & 0xFFu] & masks[(r[0] >> 8) & 0xFFu] & masks[(r[0] >> 16) & 0xFFu];
+  };
+  auto tail = [&](const u4& r, unsigned long long mk) {
+    const unsigned len = r[1] >> 24;
+    for (unsigned q = 3; q < len; ++q) mk &= masks[((q < 4 ? r[0] : r[1]) >> (8 * (q & 3))) & 0xFFu];
+    return mk;
+  };
+  auto mask_of = [&](const u4& r) { return tail(r, mask3(r)); };
+  auto add = [&](const u4& r, unsigned long long mk) {
+    const bool on = ((mk >> lane) & 1ull) != 0;
+    const unsigned long long wb = ((unsigned long long)r[3] << 32) | r[2];
+    if (J.integer)
+      si += on ? (long long)wb : 0ll;
+    else
+      sf += on ? __longlong_as_double((long long)wb) : 0.0;
+  };
+  int m = m0;
+  for (; m + 4 <= m1; m += 4) {  // four records, then their masks, in flight together
+    const u4 ra = rec[m], rb = rec[m + 1], rc = rec[m + 2], rd = rec[m + 3];
+    unsigned long long ka = mask3(ra), kb = mask3(rb), kc = mask3(rc), kd = mask3(rd);
+    asm volatile("" : "+s"(ka), "+s"(kb), "+s"(kc), "+s"(kd));  // all twelve loads before any tail branch
+    ka = tail(ra, ka);
+    kb = tail(rb, kb);
+    kc = tail(rc, kc);
+    kd = tail(rd, kd);
+    add(ra, ka);
+    add(rb, kb);
+    add(rc, kc);
+    add(rd, kd);
+  }
+  for (; m < m1; ++m) {
+    const u4 r = rec[m];
+    add(r, mask_of(r));
   }
   if (b < J.B) {
     if (J.integer)

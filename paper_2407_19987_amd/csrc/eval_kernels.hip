@@ -295,10 +295,14 @@ __global__ void reduce_partials(const void* work, void* e_out, int ncg, long lon
 // and broadcast to all lanes; the group sums are then added in group order.
 // The grouping depends only on the monomial count, so the result of a row
 // does not depend on the batch it is evaluated in.
+__global__ __launch_bounds__(256) void term_masks_one(TermJob J) {
+  if ((long long)blockIdx.x * 256 >= J.B) return;
+  term_masks(J, blockIdx.x);
+}
+
 __global__ __launch_bounds__(256) void term_partial_one(TermJob J) {
-  __shared__ TermRec srec[kTermStage];
   if ((long long)blockIdx.x * 256 >= J.B || (int)blockIdx.y * kTermGroup >= J.n_mono) return;
-  term_partial(J, blockIdx.x, blockIdx.y, srec);
+  term_partial(J, blockIdx.x, blockIdx.y);
 }
 
 // e_out[b] = sum over groups of the partial sums, in group order
@@ -403,7 +407,7 @@ int launch_eval(const EvalArgs& a, std::string* err) {
 }
 
 size_t term_workspace_bytes(const Tensor* t, int64_t B) {
-  return (size_t)term_groups(t->n_mono()) * (size_t)B * 8;
+  return term_mask_offset(t->n_mono(), B) + term_mask_bytes(t->n_vars, B);
 }
 
 int launch_term_energy(const TermArgs& a, std::string* err) {
@@ -417,6 +421,7 @@ int launch_term_energy(const TermArgs& a, std::string* err) {
   J.bits = reinterpret_cast<const unsigned long long*>(a.bits);
   J.part = a.work;
   const int G = term_groups(J.n_mono);
+  hipLaunchKernelGGL(term_masks_one, dim3((unsigned)((a.B + 255) / 256)), dim3(256), 0, st, J);
   hipLaunchKernelGGL(term_partial_one, dim3((unsigned)((a.B + 255) / 256), (unsigned)G), dim3(256), 0, st, J);
   hipLaunchKernelGGL(term_reduce_one, dim3((unsigned)((a.B + 255) / 256)), dim3(256), 0, st, J, a.e_out);
   return hip_fail(hipGetLastError(), err, "term energy launch");
