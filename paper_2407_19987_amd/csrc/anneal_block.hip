@@ -432,19 +432,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         }
       };
       unsigned wd[D];  // slot words of the round being issued
+      // (branch-free: a branch here leaves the compiler's counted waits for
+      // the ring's loads imprecise, and every round would drain the ring)
       auto fetch = [&]() {
-        if (pr.ord < nact) {
-          typedef const __attribute__((address_space(4))) u4* ConstU4;
-          const ConstU4 sp = (ConstU4)(I.sched + pr.off + pr.k);
-          const u4 a = sp[0], b = sp[1];
+        const bool past = pr.ord >= nact;  // past the last block: end slots
+        typedef const __attribute__((address_space(4))) u4* ConstU4;
+        const ConstU4 sp = (ConstU4)(I.sched + (past ? 0u : pr.off + (unsigned)pr.k));
+        const u4 a = sp[0], b = sp[1];
 #pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            wd[d] = a[d];
-            wd[4 + d] = b[d];
-          }
-        } else {
-#pragma unroll
-          for (int d = 0; d < D; ++d) wd[d] = kSlotEnd;  // past the last block
+        for (int d = 0; d < 4; ++d) {
+          wd[d] = past ? kSlotEnd : a[d];
+          wd[4 + d] = past ? kSlotEnd : b[d];
         }
       };
       // tiles and run words through buffer resources: the slot's offset is
@@ -480,8 +478,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (nact > 0) setup_block();
       BSlot<P> ring[D];
       fetch();
+      // the priming loads stay in slot order: the loop's counted waits are
+      // merged with this entry state, so a reordered priming would make
+      // every round wait for all of its loads
 #pragma unroll
-      for (int d = 0; d < D; ++d) issue(ring[d], wd[d]);
+      for (int d = 0; d < D; ++d) {
+        issue(ring[d], wd[d]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
 
       AccT<P> acc;
       acc_zero<P>(acc);
