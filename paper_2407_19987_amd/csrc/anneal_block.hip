@@ -90,11 +90,11 @@ __device__ inline int lane_id() {
 // Eight-monomial mask of a run with at most one prefix variable (all runs of
 // an order <= 3 instance's block lists): the run's byte of the replica's bits,
 // cleared when the prefix bit is 0; constant and padding runs give 1 and 0.
-__device__ inline unsigned run_mask1(unsigned d, const unsigned char* rb) {
+__device__ inline unsigned run_mask1(unsigned d, const unsigned char* rb) {  // rb[16 k] = byte k
   const unsigned np = (unsigned)(d >> 8) & 0xFFu;
   const unsigned pv = (unsigned)(d >> 16) & 0xFFu;
-  const unsigned m = rb[(unsigned)d & 0x1Fu];
-  const unsigned pb = (rb[pv >> 3] >> (pv & 7u)) & 1u;
+  const unsigned m = rb[16u * ((unsigned)d & 0x1Fu)];
+  const unsigned pb = (rb[16u * (pv >> 3)] >> (pv & 7u)) & 1u;
   const unsigned v = (np == 1u && !pb) ? 0u : m;
   return np == kRunConst ? 1u : (np == kRunNull ? 0u : v);
 }
@@ -115,14 +115,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   constexpr int RPC = PT<P>::RPC;
   constexpr int TB = P == P_FP32 ? 2048 : (P == P_BF16X2 ? 2048 : 3072);
   static_assert(D == kBlockRing, "the schedule is built in rounds of the ring depth");
-  __shared__ Luts L;
   __shared__ unsigned long long sbits[64];  // 16 replicas x 32 bytes
+  // the same bits byte-transposed, [byte][replica]: the streaming waves' reads
+  // of one byte position for 16 replicas fall in 4 consecutive banks
+  __shared__ __attribute__((aligned(16))) unsigned char sbT[32][16];
+  // nibble -> four BF16 values 0 / 1.0 (16 entries x 8 bytes: every entry in
+  // its own two banks, so the operand reads never conflict)
+  __shared__ unsigned long long sNib[16];
   __shared__ unsigned long long sbest[64];
   // per-streaming-wave partial fields, [rep][4 * sub + i] holds bit sub + 4 i
   // (two buffers: a block's early chunks run while the decisions of the one
   // before it still read its fields)
   __shared__ __attribute__((aligned(16))) float sG[2][NS][16][16];
-  __shared__ __attribute__((aligned(16))) float sH[16][16][16];  // pair couplings [rep][a][b], b < a
+  // pair couplings [rep][a][b], b < a; replicas 260 floats apart (no bank
+  // conflicts when the decision wave reads its rows as float4)
+  constexpr int kHRep = 260;
+  __shared__ __attribute__((aligned(16))) float sH[16 * kHRep];
   __shared__ unsigned short sPC[128];  // pair column -> (a << 8) | b (unused columns -> 0)
   __shared__ __attribute__((aligned(16))) float sC[NBUF][4096];  // order-3 table of the block [c][a][b]
   __shared__ __attribute__((aligned(16))) double sL[NBUF][16][16];  // -log(u) [rep][bit]
@@ -135,7 +143,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ uint2 sHdr[kMaxVars / kBlockBits][NS];
   __shared__ double strace[kSweepWin];  // per-sweep tile minima, written back after the launch's sweeps
 
-  build_luts(&L);
+  for (int n = threadIdx.x; n < 16; n += blockDim.x) {
+    unsigned long long v = 0;
+    for (int i = 0; i < 4; ++i) v |= (unsigned long long)(((n >> i) & 1) ? 0x3F80u : 0u) << (16 * i);
+    sNib[n] = v;
+  }
   for (int e = threadIdx.x; e < 128; e += blockDim.x) {
     unsigned v = 0;
     for (int a = 1; a < 16; ++a)
@@ -170,13 +182,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     if (w == 0) {
       load_bits(sbits, I.x, I.W, I.B, r0, 16, lane);
       load_bits(sbest, p.cont ? I.best_x : I.x, I.W, I.B, r0, 16, lane);
+      const unsigned char* sb = reinterpret_cast<const unsigned char*>(sbits);
+      for (int t = lane; t < 512; t += 64) sbT[t >> 4][t & 15] = sb[(t & 15) * 32 + (t >> 4)];
     }
     // the streaming waves only ever add their results to zeroed outputs;
     // wave 0 clears each output again once it has read it
     for (int e = threadIdx.x; e < 2 * NS * 64; e += blockDim.x)
       reinterpret_cast<f4*>(&sG[0][0][0][0])[e] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int e = threadIdx.x; e < 1024; e += blockDim.x)
-      reinterpret_cast<f4*>(&sH[0][0][0])[e] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int e = threadIdx.x; e < 16 * kHRep / 4; e += blockDim.x)
+      reinterpret_cast<f4*>(&sH[0])[e] = f4{0.f, 0.f, 0.f, 0.f};
     __syncthreads();
 
     // the active blocks of the launch, in stream order: every (sweep, block)
@@ -309,14 +323,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
           for (int b = 0; b < 16; ++b) {
             if (b < 4 * i + 3) {
-              const float h = sH[rep][a][b];
+              const float h = sH[rep * kHRep + a * 16 + b];
               hc[i][b] = b < a ? h : 0.0f;
             }
           }
         }
-#pragma unroll
-        for (int e = 0; e < 16; ++e)
-          reinterpret_cast<f4*>(&sH[0][0][0])[64 * e + lane] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int e = lane; e < 16 * kHRep / 4; e += 64)
+          reinterpret_cast<f4*>(&sH[0])[e] = f4{0.f, 0.f, 0.f, 0.f};
         unsigned char* myb = reinterpret_cast<unsigned char*>(sbits) + rep * 32 + 2 * q;
         unsigned xb = (unsigned)myb[0] | ((unsigned)myb[1] << 8);
 #pragma unroll
@@ -359,6 +372,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         if (sub == 0) {
           myb[0] = (unsigned char)(xb & 0xFFu);
           myb[1] = (unsigned char)(xb >> 8);
+          sbT[2 * q][rep] = (unsigned char)(xb & 0xFFu);
+          sbT[2 * q + 1][rep] = (unsigned char)(xb >> 8);
         }
         lds_barrier();  // B
       }
@@ -489,7 +504,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 
       AccT<P> acc;
       acc_zero<P>(acc);
-      const unsigned char* rb = reinterpret_cast<const unsigned char*>(sbits) + j * 32;
+      const unsigned char* rb = &sbT[0][j];
       // one round of D slots: the operand of slot d + 1 is generated before
       // the matrix-core work of slot d, so its LDS reads overlap that work
       auto round = [&](float* myG) {
@@ -504,7 +519,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
           if constexpr (P == P_FP32) {
             a.v = u4{msk, 0u, 0u, 0u};
           } else {
-            a.v = L.bf16[msk];
+            const unsigned long long lo = sNib[msk & 15u], hi = sNib[msk >> 4];
+            a.v = u4{(unsigned)lo, (unsigned)(lo >> 32), (unsigned)hi, (unsigned)(hi >> 32)};
           }
           return a;
         };
@@ -521,9 +537,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
               for (int r = 0; r < 4; ++r) myG[16 * r] = acc.v[r];
             } else {
               const unsigned ab = sPC[16 * (sl.tgt - 1) + j];
-              float* dst = &sH[4 * g][ab >> 8][ab & 0xFFu];
+              float* dst = &sH[4 * g * kHRep + (ab >> 8) * 16 + (ab & 0xFFu)];
 #pragma unroll
-              for (int r = 0; r < 4; ++r) dst[256 * r] = acc.v[r];
+              for (int r = 0; r < 4; ++r) dst[kHRep * r] = acc.v[r];
             }
             acc_zero<P>(acc);
           }
