@@ -99,10 +99,11 @@ __device__ inline unsigned run_mask1(unsigned d, const unsigned char* rb) {  // 
   return np == kRunConst ? 1u : (np == kRunNull ? 0u : v);
 }
 
-// At most 128 VGPRs: four waves per SIMD (one 16-wave group, or several
-// narrower ones, per CU).
+// Eight- and sixteen-wave groups keep to 128 VGPRs (four waves per SIMD);
+// the two- and four-wave forms, whose streaming waves each carry more of the
+// block, may use twice that and run two waves per SIMD.
 template <int P, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void anneal_block_kernel(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8 ? 4 : 2))) void anneal_block_kernel(
     AnnealParams p) {
   static_assert(NW >= 2, "one decision wave and at least one streaming wave");
   // with sixteen waves, wave 1 stages the next block's table and uniforms
