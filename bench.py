@@ -78,7 +78,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the replicas are independent and "
-              "would shard across GPUs, which this build does not run)", file=sys.stderr)
+              "would shard across GPUs, but only the one-GPU path is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
