@@ -223,7 +223,12 @@ typedef struct {
  *  launch_mode : PER_INSTANCE (one launch sequence per instance),
  *                PERSISTENT (one persistent launch over all instances), or
  *                GRAPH (the persistent sequence captured once in a hipGraph
- *                and launched from it) -- identical results */
+ *                and launched from it) -- identical results
+ * The library keeps the device setup of recent calls (tables, a workspace of
+ * up to about 1 GiB of Metropolis uniforms per call, the captured graph), keyed
+ * by every argument including the buffer pointers, so a repeated call only
+ * launches.  It keeps at most 16 setups, the older ones holding at most 4 GiB;
+ * hobo_free_tensor releases the setups that name its tensor. */
 hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances,
                               const int64_t* replicas, const hobo_anneal_params* params,
                               uint64_t* x_inout, uint64_t* best_x_out, void* best_e_out,

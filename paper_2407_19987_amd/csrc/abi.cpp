@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <iterator>
 #include <list>
 #include <mutex>
 #include <string>
@@ -105,10 +106,16 @@ hobo_status check_bits_args(const hobo_tensor* t, const void* x_bits, int64_t B,
 // Annealing setups (device tables, workspace, captured graph) are cached by
 // their full argument list, so repeated identical calls only enqueue kernels
 // (or launch the graph).  Entries that name a tensor die with it.
+// At most kAnnealKeep setups are kept, and the older ones together hold at
+// most kAnnealKeepBytes of workspace (calls that differ only in the seed each
+// make a setup).
+constexpr size_t kAnnealKeep = 16;
+constexpr size_t kAnnealKeepBytes = (size_t)4 << 30;
 struct AnnealEntry {
   std::vector<uint64_t> key;
   int32_t mode = 0;
   void* work = nullptr;
+  size_t bytes = 0;  // workspace size
   hobo::AnnealTables tb;
   std::vector<hobo::AnnealPlan> plans;  // PERSISTENT / GRAPH: one plan; PER_INSTANCE: one per instance
   hipGraphExec_t exec = nullptr;
@@ -666,6 +673,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     ne.key = key;
     ne.mode = launch_mode;
     if (hobo_status hs = hip_status(hipMalloc(&ne.work, total), "hipMalloc")) return hs;
+    ne.bytes = total;
     char* wb = static_cast<char*>(ne.work);
     std::vector<hobo::AnnealInstDev> inst((size_t)n_instances);
     std::vector<hobo::InstSmall> small((size_t)n_instances);
@@ -867,7 +875,10 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     }
     g_anneal.push_front(std::move(ne));
     ent = &g_anneal.front();
-    while (g_anneal.size() > 16) {
+    size_t older = 0;
+    for (auto it = std::next(g_anneal.begin()); it != g_anneal.end(); ++it) older += it->bytes;
+    while (g_anneal.size() > 1 && (g_anneal.size() > kAnnealKeep || older > kAnnealKeepBytes)) {
+      older -= g_anneal.back().bytes;
       release_entry(g_anneal.back());
       g_anneal.pop_back();
     }

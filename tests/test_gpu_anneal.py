@@ -108,6 +108,21 @@ def test_blocked_trajectory_identity(env, n, k, dens, nw):
     assert_same(g, o)
 
 
+def test_setups_released_and_rebuilt(env):
+    """More distinct calls than the library keeps setups for: the first call's
+    setup is released and later built again, and the repeated call still runs
+    the oracle's chain."""
+    hobo, _ = env
+    terms = _int_instance(7, 40, 3, lo=-4, hi=4, dens=0.5)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    o = oracle.anneal(c, 32, 6, 4.0, 0.1, seed=1000)
+    assert_same(run_gpu(env, t, 32, 6, 4.0, 0.1, seed=1000, prec=1, algo=BLOCKS, nw=2)[0], o)
+    for k in range(20):
+        run_gpu(env, t, 32, 6, 4.0, 0.1, seed=2000 + k, prec=1, algo=BLOCKS, nw=2)
+    assert_same(run_gpu(env, t, 32, 6, 4.0, 0.1, seed=1000, prec=1, algo=BLOCKS, nw=2)[0], o)
+
+
 def test_blocked_masks_across_windows(env):
     """Attempt masks with more sweeps than one masked launch covers (the
     blocked kernel runs masked calls in windows of 64 sweeps); whole blocks
