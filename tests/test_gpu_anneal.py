@@ -108,6 +108,18 @@ def test_blocked_trajectory_identity(env, n, k, dens, nw):
     assert_same(g, o)
 
 
+def test_intenc4_full_batch_trajectory(env):
+    """Annealing the order-4 integer-encoded workload with INT8X4 limbs at its
+    full batch of 8192 replicas runs the oracle's chain exactly."""
+    hobo, _ = env
+    terms = W.cfg_intenc4(seed=0)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    g = run_gpu(env, t, 8192, 8, 2e4, 50.0, seed=31, prec=3)[0]
+    o = oracle.anneal(c, 8192, 8, 2e4, 50.0, seed=31)
+    assert_same(g, o)
+
+
 def test_setups_released_and_rebuilt(env):
     """More distinct calls than the library keeps setups for: the first call's
     setup is released and later built again, and the repeated call still runs

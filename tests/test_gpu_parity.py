@@ -146,6 +146,21 @@ def test_intenc4_int8_bit_exact(env):
     assert ei.value.code == hobo.ERR_RANGE
 
 
+def test_intenc4_full_batch_int8_bit_exact(env):
+    """The order-4 integer-encoded workload at its full batch of 8192 replicas:
+    INT8X4 energies and flip changes equal the oracle's on every row."""
+    hobo, _ = env
+    terms = W.cfg_intenc4(seed=0)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(48, 8192, seed=21))
+    want = oracle.energy(c, bits)
+    np.testing.assert_array_equal(gpu_energy(env, t, bits, 3), want)
+    de, e = gpu_fields(env, t, bits, 3)
+    np.testing.assert_array_equal(de, oracle.fields(c, bits)[1])
+    np.testing.assert_array_equal(e, want)
+
+
 def test_degenerate_instances(env):
     hobo, torch = env
     # no monomials at all (constant only)
