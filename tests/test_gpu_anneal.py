@@ -260,3 +260,23 @@ def test_real_instance_rescored_energies(env, prec):
     # same chain up to near-ties: the best energies agree closely in distribution
     assert abs(np.median(g["best_e"]) - np.median(o["best_e"])) < 0.05 * abs(np.median(o["best_e"])) + 1e-3
     assert g["trace"][-1] <= g["trace"][0]
+
+
+def test_real3_full_size_blocked_anneal(env):
+    """The annealing workload at full size in the benchmark's launch shape
+    (N=128 order 3, 4096 replicas, 1000 sweeps, BF16X2, sixteen-wave blocked
+    groups).  Every reported best energy is the FP64 energy of the reported
+    best state, the trace never rises, and the first 16 replicas reach the
+    oracle's best energies up to near-tie divergence."""
+    hobo, _ = env
+    terms = W.cfg_real3(seed=0)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    g = run_gpu(env, t, 4096, 1000, 5.0, 0.01, seed=42, prec=1, algo=BLOCKS, nw=16)[0]
+    want = oracle.energy(c, g["best_bits"])
+    rows = np.random.default_rng(1).choice(4096, size=64, replace=False)
+    floor = float(np.median(oracle.active_scale(c, g["best_bits"][:, rows])))
+    assert (np.abs(g["best_e"] - want) <= 1e-12 * np.maximum(np.abs(want), floor)).all()
+    assert (np.diff(g["trace"]) <= 0).all()
+    o = oracle.anneal(c, 16, 1000, 5.0, 0.01, seed=42)
+    assert abs(np.median(g["best_e"][:16]) - np.median(o["best_e"])) < 0.02 * abs(np.median(o["best_e"]))
