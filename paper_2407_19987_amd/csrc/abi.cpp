@@ -99,6 +99,10 @@ hobo_status check_bits_args(const hobo_tensor* t, const void* x_bits, int64_t B,
   if (!valid_prec(precision)) return fail(HOBO_ERR_INVALID_ARG, "unknown precision");
   if (precision == HOBO_PREC_INT8X4 && !t->t.integer)
     return fail(HOBO_ERR_PRECISION, "INT8X4 precision needs an integer tensor");
+  if (precision != HOBO_PREC_FP64) {
+    std::string err;
+    if (int s = hobo::check_prec(&t->t, precision, &err)) return fail(s, err);
+  }
   return HOBO_OK;
 }
 
@@ -354,6 +358,11 @@ hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_
   if (!t) return fail(HOBO_ERR_INVALID_ARG, "tensor is NULL");
   if (fn_mask & ~7u) return fail(HOBO_ERR_INVALID_ARG, "unknown function bits");
   if (prec_mask & ~31u) return fail(HOBO_ERR_INVALID_ARG, "unknown precision bits");
+  for (int p = 0; p < HOBO_PREC_FP64; ++p) {
+    std::string e;
+    if ((prec_mask & (1u << p)) && fn_mask)
+      if (int s = hobo::check_prec(&t->t, p, &e)) return fail(s, e);
+  }
   if (hobo_status s = need_device()) return s;
   std::string err;
   for (int p = 0; p <= HOBO_PREC_FP64; ++p) {
@@ -508,6 +517,10 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   if (P.precision == HOBO_PREC_INT8X4 && !all_int) return fail(HOBO_ERR_PRECISION, "INT8X4 needs integer tensors");
   if (P.precision == HOBO_PREC_INT8X4 && max_n > 64)
     return fail(HOBO_ERR_UNSUPPORTED, "INT8X4 annealing supports at most 64 variables");
+  for (int j = 0; j < n_instances; ++j) {
+    std::string e;
+    if (int s = hobo::check_prec(&tensors[j]->t, P.precision, &e)) return fail(s, e);
+  }
   // kernel of each instance: blocked where it applies (and is not overridden)
   std::vector<int> blocked((size_t)n_instances);
   for (int j = 0; j < n_instances; ++j) {

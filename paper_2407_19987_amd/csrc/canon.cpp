@@ -8,11 +8,98 @@
 #include <cstring>
 #include <string>
 #include <unordered_map>
+#include <utility>
 
 #include "hobo_internal.h"
 #include "../../include/hobo.h"
 
 namespace hobo {
+
+namespace {
+
+// Exact sum of doubles, rounded once to the nearest double (ties to even).
+// Every finite double is an integer multiple of 2^-1074, so the sum is kept
+// as one wide two's-complement integer in units of 2^-1074 (a Kulisch-style
+// long accumulator: 2098 bits cover the whole double range, the rest is
+// headroom for carries of up to 2^60 terms).  Duplicate monomials and the
+// constant terms go through it, so their sums do not depend on term order.
+class ExactSum {
+ public:
+  static constexpr int kLimbs = 35;  // 2240 bits
+  ExactSum() { std::memset(l_, 0, sizeof(l_)); }
+  void add(double d) {
+    if (d == 0.0) return;
+    int e = 0;
+    const double m = std::frexp(std::fabs(d), &e);        // |d| = m 2^e, 0.5 <= m < 1
+    uint64_t M = (uint64_t)std::ldexp(m, 53);              // 53-bit integer significand
+    int sh = e - 53 + 1074;                                 // |d| = M 2^(sh - 1074)
+    if (sh < 0) {                                           // subnormal: M has trailing zeros
+      M >>= -sh;
+      sh = 0;
+    }
+    const int q = sh >> 6, b = sh & 63;
+    const uint64_t lo = M << b, hi = b ? (M >> (64 - b)) : 0;
+    if (d > 0)
+      add_at(q, lo, hi);
+    else
+      sub_at(q, lo, hi);
+  }
+  // nearest double of the exact sum (+-inf if it is out of range)
+  double value() const {
+    uint64_t v[kLimbs];
+    std::memcpy(v, l_, sizeof(v));
+    const bool neg = (v[kLimbs - 1] >> 63) != 0;
+    if (neg) {  // two's-complement magnitude
+      unsigned carry = 1;
+      for (int i = 0; i < kLimbs; ++i) {
+        const uint64_t x = ~v[i] + carry;
+        carry = (carry && x == 0) ? 1u : 0u;
+        v[i] = x;
+      }
+    }
+    int top = -1;  // highest set bit
+    for (int i = kLimbs - 1; i >= 0 && top < 0; --i)
+      if (v[i]) top = 64 * i + 63 - __builtin_clzll(v[i]);
+    if (top < 0) return 0.0;
+    auto bit = [&](int p) { return (int)((v[p >> 6] >> (p & 63)) & 1u); };
+    double r;
+    if (top < 53) {  // exact: fewer than 54 significant bits
+      uint64_t x = v[0];
+      r = std::ldexp((double)x, -1074);
+    } else {
+      const int cut = top - 52;  // bits below `cut` are rounded off
+      uint64_t q = 0;
+      for (int p = top; p >= cut; --p) q = (q << 1) | (uint64_t)bit(p);
+      const int half = bit(cut - 1);
+      bool sticky = false;  // any set bit below the half-way bit
+      for (int p = 0; p <= cut - 2 && !sticky; ++p) sticky = bit(p) != 0;
+      if (half && (sticky || (q & 1u))) ++q;
+      r = std::ldexp((double)q, cut - 1074);
+    }
+    return neg ? -r : r;
+  }
+
+ private:
+  void add_at(int q, uint64_t lo, uint64_t hi) {
+    unsigned __int128 c = (unsigned __int128)l_[q] + lo;
+    l_[q] = (uint64_t)c;
+    c = (unsigned __int128)l_[q + 1] + hi + (uint64_t)(c >> 64);
+    l_[q + 1] = (uint64_t)c;
+    uint64_t carry = (uint64_t)(c >> 64);
+    for (int i = q + 2; carry && i < kLimbs; ++i) carry = (++l_[i] == 0) ? 1u : 0u;
+  }
+  void sub_at(int q, uint64_t lo, uint64_t hi) {
+    uint64_t borrow = l_[q] < lo ? 1u : 0u;
+    l_[q] -= lo;
+    const unsigned __int128 need = (unsigned __int128)hi + borrow;
+    borrow = (unsigned __int128)l_[q + 1] < need ? 1u : 0u;
+    l_[q + 1] -= (uint64_t)need;
+    for (int i = q + 2; borrow && i < kLimbs; ++i) borrow = (l_[i]-- == 0) ? 1u : 0u;
+  }
+  uint64_t l_[kLimbs];
+};
+
+}  // namespace
 
 int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term_ptr,
                  const int32_t* term_idx, const void* coeff, int coeff_type, Tensor* t,
@@ -24,9 +111,10 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
   std::unordered_map<std::string, size_t> where;
   std::vector<std::string> keys;
   std::vector<int64_t> acc_i;
-  std::vector<double> acc_f;
+  std::vector<double> acc_f;  // real: the first value of each monomial
+  std::vector<std::pair<size_t, double>> dup_f;  // real: further values (slot, value)
   int64_t off_i = 0;
-  double off_f = 0.0;
+  ExactSum off_f;
   std::vector<int> buf;
   for (int64_t term = 0; term < n_terms; ++term) {
     int64_t a = term_ptr[term], b = term_ptr[term + 1];
@@ -51,7 +139,7 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
           return HOBO_ERR_RANGE;
         }
       } else {
-        off_f += cf[term];
+        off_f.add(cf[term]);
       }
       continue;
     }
@@ -59,7 +147,8 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
     for (size_t j = 0; j < buf.size(); ++j) key[j] = (char)(uint8_t)buf[j];
     auto it = where.find(key);
     size_t slot;
-    if (it == where.end()) {
+    const bool fresh = it == where.end();
+    if (fresh) {
       slot = keys.size();
       where.emplace(key, slot);
       keys.push_back(key);
@@ -73,8 +162,28 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
         *err = "integer coefficient sum overflows int64";
         return HOBO_ERR_RANGE;
       }
+    } else if (fresh) {
+      acc_f[slot] = cf[term];
     } else {
-      acc_f[slot] += cf[term];
+      dup_f.emplace_back(slot, cf[term]);
+    }
+  }
+  // duplicate real monomials: the exact sum of all their values, rounded once
+  if (!dup_f.empty()) {
+    std::stable_sort(dup_f.begin(), dup_f.end(),
+                     [](const std::pair<size_t, double>& a, const std::pair<size_t, double>& b) {
+                       return a.first < b.first;
+                     });
+    for (size_t i = 0; i < dup_f.size();) {
+      const size_t slot = dup_f[i].first;
+      ExactSum es;
+      es.add(acc_f[slot]);
+      for (; i < dup_f.size() && dup_f[i].first == slot; ++i) es.add(dup_f[i].second);
+      acc_f[slot] = es.value();
+      if (!std::isfinite(acc_f[slot])) {
+        *err = "a real coefficient sum overflows double";
+        return HOBO_ERR_RANGE;
+      }
     }
   }
   // keep non-zero monomials, ordered by (size, lexicographic)
@@ -99,6 +208,8 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
   t->w_i.clear();
   t->w_f.clear();
   t->n_per_order.assign((size_t)k + 1, 0);
+  t->abs_sum = 0;
+  t->w_lo = t->w_hi = 0;
   t->row_norm.assign((size_t)n_vars, 0.0);
   for (size_t s : order) {
     const std::string& key = keys[s];
@@ -108,6 +219,12 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
     t->w_i.push_back(integer ? acc_i[s] : 0);
     t->w_f.push_back(w);
     t->n_per_order[key.size()]++;
+    if (integer) {
+      const __int128 v = acc_i[s];
+      t->abs_sum += (unsigned __int128)(v < 0 ? -v : v);
+      t->w_lo = std::min(t->w_lo, acc_i[s]);
+      t->w_hi = std::max(t->w_hi, acc_i[s]);
+    }
     for (char c : key) t->row_norm[(uint8_t)c] += w * w;
   }
   t->row_norm_max = 0.0;
@@ -116,7 +233,12 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
     t->row_norm_max = std::max(t->row_norm_max, v);
   }
   t->offset_i = off_i;
-  t->offset_f = integer ? (double)off_i : off_f;
+  const double off_real = off_f.value();
+  if (!integer && !std::isfinite(off_real)) {
+    *err = "the constant offset overflows double";
+    return HOBO_ERR_RANGE;
+  }
+  t->offset_f = integer ? (double)off_i : off_real;
   return HOBO_OK;
 }
 

@@ -151,6 +151,8 @@ struct Tensor {
   int64_t offset_i = 0;
   double offset_f = 0.0;
   std::vector<int64_t> n_per_order;  // [order+1]
+  unsigned __int128 abs_sum = 0;     // integer tensors: sum |w| (exact)
+  int64_t w_lo = 0, w_hi = 0;        // integer tensors: smallest and largest weight
   double row_norm_max = 0.0;
   std::vector<double> row_norm;  // ||H_i||_2 over monomials containing i
 
@@ -183,6 +185,10 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
                  const int32_t* term_idx, const void* coeff, int coeff_type, Tensor* t,
                  std::string* err);
 
+// pack.cpp -- whether a precision can represent the tensor exactly enough
+// (host-only checks: INT8X4 needs an integer tensor whose digit and energy
+// sums fit; FP32 / BF16 on an integer tensor need sum |w| < 2^24)
+int check_prec(const Tensor* t, int prec, std::string* err);
 // pack.cpp -- build (once) the packed layout; returns a status code
 int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err);
 // the blocked annealer's schedule for nw-wave work-groups (built on first use)

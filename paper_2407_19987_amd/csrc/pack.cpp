@@ -293,24 +293,45 @@ int upload(const std::vector<T>& v, T** dst, size_t* bytes, std::string* err) {
   return HOBO_OK;
 }
 
+}  // namespace
+
 int check_prec(const Tensor* t, int prec, std::string* err) {
   if (prec == P_INT8X4 && !t->integer) {
     *err = "INT8X4 precision needs an integer tensor";
     return HOBO_ERR_PRECISION;
   }
+  if (prec == P_INT8X4) {
+    // four balanced base-256 digits hold -128 * 0x01010101 .. 127 * 0x01010101
+    constexpr int64_t kDigitsLo = -128LL * 0x01010101LL, kDigitsHi = 127LL * 0x01010101LL;
+    if (t->w_lo < kDigitsLo || t->w_hi > kDigitsHi) {
+      *err = "INT8X4: an integer coefficient exceeds four INT8 digits";
+      return HOBO_ERR_RANGE;
+    }
+    // Each digit pass sums 0/1 products of digits in [-128, 127] over at most
+    // every monomial of the instance into an int32 lane: 128 * n_mono must
+    // stay below 2^31.  The fields kernel's energy carries the per-order sums
+    // scaled by lcm(1..7) = 420 with up to `order` fields per monomial, in
+    // int64: 420 * order * sum |w| must stay below 2^63 (which also keeps the
+    // annealer's tracked energies exact in double).
+    if ((int64_t)t->n_mono() >= ((int64_t)1 << 24)) {
+      *err = "INT8X4: more than 2^24 monomials would overflow the int32 digit sums";
+      return HOBO_ERR_RANGE;
+    }
+    const unsigned __int128 lim = ((unsigned __int128)1 << 63) / (unsigned __int128)(420 * std::max(t->order, 1));
+    if (t->abs_sum >= lim) {
+      *err = "INT8X4: 420 * order * sum |w| would overflow the int64 energy sums";
+      return HOBO_ERR_RANGE;
+    }
+  }
   if (t->integer && (prec == P_FP32 || prec == P_BF16X2 || prec == P_BF16X3)) {
     // every partial sum of an FP32 accumulation must be an exact integer
-    double s = 0.0;
-    for (auto w : t->w_i) s += std::fabs((double)w);
-    if (s >= 16777216.0) {
+    if (t->abs_sum >= ((unsigned __int128)1 << 24)) {
       *err = "integer tensor with sum |w| >= 2^24 cannot be exact in FP32 accumulation; use INT8X4";
       return HOBO_ERR_RANGE;
     }
   }
   return HOBO_OK;
 }
-
-}  // namespace
 
 int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
   std::lock_guard<std::mutex> lock(t->mu);

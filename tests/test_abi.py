@@ -3,6 +3,8 @@ of include/hobo.h, the host-side compile step agrees with the oracle's
 independent canonicaliser, the dense export follows the paper's layout, and
 invalid arguments are rejected before any device work."""
 import ctypes
+import itertools
+import math
 import os
 import re
 
@@ -120,3 +122,60 @@ def test_no_device_is_reported_without_gpu(hobo):
     q = ctypes.c_void_p(16)
     assert hobo.lib.hobo_energy(t.handle, q, 4, 0, q, None) == hobo.ERR_NO_DEVICE
     assert hobo.lib.hobo_tensor_prepare(t.handle, 1, 1) == hobo.ERR_NO_DEVICE
+
+
+def test_duplicate_real_terms_sum_correctly_rounded(hobo):
+    """Duplicate monomials and constant terms are summed exactly and rounded
+    once, like the oracle's fsum: the result does not depend on term order,
+    and cancellation (1e16 + 1 - 1e16 = 1), subnormal parts and values many
+    binades apart come out as the correctly rounded sum."""
+    rng = np.random.default_rng(5)
+    groups = [[1e16, 1.0, -1e16], [2.0 ** -1074, 2.0 ** -1074, 1e-310], [1e300, -1e300, 3.5e-300, 1e-320],
+              [0.1] * 10, [1.0, 2.0 ** -53, 2.0 ** -53], [1.0, 2.0 ** -53], [1.0, 2.0 ** -53, 2.0 ** -105],
+              [-1.0, -(2.0 ** -53), -(2.0 ** -106)], [5e-324, -5e-324], [1e308, 1e308, -1e308]]
+    for _ in range(40):
+        k = int(rng.integers(2, 30))
+        groups.append(list(rng.standard_normal(k) * 10.0 ** rng.integers(-300, 300, size=k)))
+    terms = []
+    for g, vals in enumerate(groups):
+        mono = (g % 7, 7 + g // 7)  # distinct pairs over 16 variables
+        for v in vals:
+            terms.append((mono[::-1] if rng.random() < 0.5 else mono, float(v)))
+    for v in groups[0] + groups[3]:
+        terms.append(((), float(v)))
+    order = rng.permutation(len(terms))
+    raw = W.RawPoly([terms[i] for i in order])
+    tt = W.poly_to_terms(16, raw, False)
+    c = oracle.canonicalize(tt)
+    t = hobo.Tensor.from_terms(tt)
+    ptr, idx, w = t.monomials()
+    got = {tuple(idx[ptr[m]:ptr[m + 1]].tolist()): float(w[m]) for m in range(len(w))}
+    assert got == dict(zip(c.monos, c.weights))
+    assert t.offset == c.offset
+    assert t.offset == math.fsum(groups[0] + groups[3])
+
+
+def test_int8_and_float_range_refused_on_host(hobo):
+    """Precisions that cannot hold an integer tensor exactly are refused with
+    HOBO_ERR_RANGE before any device call (so also without a GPU): a weight
+    beyond four INT8 digits, FP32 / BF16 sums with sum |w| >= 2^24, and an
+    instance whose 420 * order * sum |w| would overflow the int64 energy sums
+    of the INT8X4 kernels."""
+    q = ctypes.c_void_p(16)
+    lim = 127 * 0x01010101
+    t = hobo.Tensor.from_terms(W.poly_to_terms(3, W.RawPoly([((0,), lim + 1), ((1, 2), 3)]), True))
+    assert hobo.lib.hobo_energy(t.handle, q, 4, hobo.PREC_INT8X4, q, None) == hobo.ERR_RANGE
+    assert hobo.lib.hobo_local_fields(t.handle, q, 4, hobo.PREC_INT8X4, q, None, None) == hobo.ERR_RANGE
+    assert hobo.lib.hobo_tensor_prepare(t.handle, 1, 1 << hobo.PREC_INT8X4) == hobo.ERR_RANGE
+    assert hobo.lib.hobo_energy(t.handle, q, 4, hobo.PREC_FP32, q, None) == hobo.ERR_RANGE
+    t = hobo.Tensor.from_terms(W.poly_to_terms(3, W.RawPoly([((0,), lim), ((1, 2), -(2 ** 20))]), True))
+    assert hobo.lib.hobo_energy(t.handle, q, 4, hobo.PREC_BF16X2, q, None) == hobo.ERR_RANGE
+    # order 7 with 1.5M monomials of weight lim: 2940 * sum|w| > 2^63
+    n, k, m = 40, 7, 1_500_000
+    combos = np.array(list(itertools.islice(itertools.combinations(range(n), k), m)), dtype=np.int32)
+    terms = W.TermList(n, np.arange(0, k * m + 1, k, dtype=np.int64), combos.reshape(-1),
+                    np.full(m, lim, dtype=np.int64))
+    t = hobo.Tensor.from_terms(terms)
+    assert 2940 * lim * m >= 2 ** 63
+    assert hobo.lib.hobo_energy(t.handle, q, 4, hobo.PREC_INT8X4, q, None) == hobo.ERR_RANGE
+    assert "int64" in hobo.lib.hobo_last_error().decode()

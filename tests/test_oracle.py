@@ -325,3 +325,79 @@ def test_anneal_schedule_split_matches_whole_run():
     np.testing.assert_array_equal(np.minimum(a["trace"][-1], b["trace"]), whole["trace"][11:])
     with pytest.raises(ValueError):
         oracle.anneal(c, 4, 10, 3.0, 0.1, seed=4, first_sweep=20, schedule_sweeps=25)
+
+
+# ------------------------------------------------ tolerance scales and schedule
+
+
+def _hand_instance():
+    """Four variables with hand-picked weights whose squares give whole sums:
+    a_0 = 3, a_1 = -4, b_01 = 12, b_23 = 84, c_123 = 2."""
+    p = W.RawPoly([((0,), 3.0), ((1,), -4.0), ((0, 1), 12.0), ((2, 3), 84.0), ((1, 2, 3), 2.0)])
+    return _canon(W.poly_to_terms(4, p, False))
+
+
+def test_active_scale_by_hand():
+    """s(x) = (sum over monomials with every variable set of w_S^2)^(1/2),
+    the floor of the relative-error criterion.  Hand values: x = 1100 keeps
+    a_0, a_1, b_01 (9 + 16 + 144 = 13^2); x = 0011 keeps b_23 (84); x = 1111
+    keeps all five (7229); x = 0 keeps none.  A sum of |w| (19 at 1100), a
+    missing root (169) or an RMS over the active terms (13 / sqrt 3) all
+    differ from these."""
+    c = _hand_instance()
+    x = np.array([[1, 1, 0, 0], [0, 0, 1, 1], [1, 1, 1, 1], [0, 0, 0, 0], [0, 1, 1, 1]], dtype=np.uint8)
+    got = oracle.active_scale(c, W.pack_bits(x))
+    want = [13.0, 84.0, math.sqrt(9 + 16 + 144 + 7056 + 4), 0.0, math.sqrt(16 + 7056 + 4)]
+    np.testing.assert_allclose(got, want, rtol=1e-15, atol=0)
+
+
+def test_field_scale_by_hand():
+    """s_i(x) = (sum over monomials S containing i whose other variables are
+    all set of w_S^2)^(1/2): the bit's own value does not enter.  At
+    x = 0111: bit 0 sees a_0 and b_01 (9 + 144); bit 1 sees a_1 and c_123
+    (16 + 4; b_01 is off since x_0 = 0); bits 2 and 3 see b_23 and c_123
+    (7056 + 4).  At x = 0011 bit 0 sees a_0 only (3) even though x_0 = 0,
+    and bit 1 sees a_1 and c_123 (20)."""
+    c = _hand_instance()
+    x = np.array([[0, 1, 1, 1], [0, 0, 1, 1], [0, 0, 0, 0]], dtype=np.uint8)
+    got = oracle.field_scale(c, W.pack_bits(x))
+    want = [[math.sqrt(153), math.sqrt(20), math.sqrt(7060), math.sqrt(7060)],
+            [3.0, math.sqrt(20), 84.0, 84.0],
+            [3.0, 4.0, 0.0, 0.0]]
+    np.testing.assert_allclose(got, want, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("t0,t1,S", [(5.0, 0.01, 1000), (2.0, 3.0, 7), (1.0, 1.0, 4), (0.5, 0.25, 2)])
+def test_schedule_is_geometric_from_t_start_to_t_end(t0, t1, S):
+    """The reading of Sec. II.D.1's cooling: S temperatures, the first t_start,
+    the last t_end, every ratio T_{s+1}/T_s the same (t_end/t_start)^(1/(S-1))."""
+    T = oracle.schedule(t0, t1, S)
+    assert len(T) == S
+    assert T[0] == t0
+    assert abs(T[-1] - t1) <= 4e-16 * t1
+    r = (t1 / t0) ** (1.0 / (S - 1))
+    np.testing.assert_allclose(T[1:] / T[:-1], r, rtol=1e-13, atol=0)
+    assert (np.diff(T) < 0).all() if t1 < t0 else (np.diff(T) >= 0).all()
+
+
+def test_schedule_single_sweep_is_t_start():
+    np.testing.assert_array_equal(oracle.schedule(3.0, 0.1, 1), [3.0])
+
+
+def test_anneal_uses_the_schedule_temperature_each_sweep():
+    """The chain runs at the schedule's temperature: one replica on one
+    variable with a_0 = 1 starting at x = 0 flips up in sweep s iff
+    u_s < exp(-1 / T_s), with u_s the acceptance draw of (replica 0, sweep s,
+    bit 0) from Philox word 0 at counter (0, s, 0, 0), key (seed, 0)."""
+    c = _canon(W.poly_to_terms(1, W.RawPoly([((0,), 1.0)]), False))
+    S, seed = 6, 31
+    T = oracle.schedule(4.0, 0.5, S)
+    x = np.zeros((1, 1), dtype=np.uint64)
+    for s in range(S):
+        res = oracle.anneal(c, 1, 1, 4.0, 0.5, seed=seed, init_bits=x, first_sweep=s, schedule_sweeps=S)
+        word = int(oracle.philox4x64(np.array([0, s, 0, 0], dtype=np.uint64), (seed, 0))[0])
+        u = (word >> 11) * 2.0 ** -53
+        up = int(x[0, 0]) == 0
+        flips = (not up) or u < math.exp(-1.0 / T[s])  # dE = -1 going down is always taken
+        assert int(res["final_bits"][0, 0]) == (int(x[0, 0]) ^ int(flips))
+        x = res["final_bits"]
