@@ -68,10 +68,12 @@ def _load():
         lib.orc_brute_force.restype = i32
         lib.orc_philox4x64.argtypes = [P, P, P]
         lib.orc_philox4x64.restype = None
-        lib.orc_anneal.argtypes = [i32, i32, P, P, P, i32, i64, i32, P, u64, u64, i32, P, P, P, P, P, P, P, i32]
+        lib.orc_anneal.argtypes = [i32, i32, P, P, P, i32, i64, i32, P, u64, u64, i32, P, P, P, P, P, P, P, i32, P]
         lib.orc_anneal.restype = i32
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = i32
+        lib.orc_set_threads.argtypes = [i32]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -82,6 +84,11 @@ def _p(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops (for timing)."""
+    _load().orc_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------
@@ -369,14 +376,18 @@ def schedule(t_start: float, t_end: float, sweeps: int) -> np.ndarray:
 
 def anneal(canon: Canonical, n_rep: int, sweeps: int, t_start: float, t_end: float, seed: int,
            inst: int = 0, init_bits: np.ndarray | None = None, attempt: np.ndarray | None = None,
-           first_sweep: int = 0, schedule_sweeps: int = 0):
+           first_sweep: int = 0, schedule_sweeps: int = 0, margins: bool = False):
     """Batched Metropolis annealing; see orc_anneal in oracle.c for the rules.
 
     Runs sweeps first_sweep .. first_sweep+sweeps-1 of a geometric schedule of
     schedule_sweeps sweeps (default: the whole schedule, first_sweep 0); the
     sweep index is the one of the schedule (temperature and random draws).
     Returns dict(final_bits [W][B], best_bits [W][B], best_e (exact, int64 or
-    float64), trace [S], accepts); the best state starts at the start state."""
+    float64), trace [S], accepts); the best state starts at the start state.
+    With margins=True also margin [B][S]: per replica and sweep the smallest
+    relative decision margin |dE beta + ln u| / (beta A) (A = sum of |w| of
+    the active monomials of the visited bit), the fraction of A by which an
+    inexact dE may err before it could change a decision of that sweep."""
     n = canon.n_vars
     w = (n + 63) // 64
     ptr, idx = canon.csr()
@@ -392,12 +403,17 @@ def anneal(canon: Canonical, n_rep: int, sweeps: int, t_start: float, t_end: flo
     trace = np.zeros(max(sweeps, 1), dtype=np.float64)
     nacc = np.zeros(1, dtype=np.int64)
     att = None if attempt is None else np.ascontiguousarray(attempt, dtype=np.uint8)
+    marg = np.full((n_rep, max(sweeps, 1)), np.inf, dtype=np.float64) if margins else None
     rc = _load().orc_anneal(n, len(co), _p(ptr), _p(idx), _p(co), s, n_rep, sweeps, _p(temps), seed, inst,
                             1 if init_bits is not None else 0, _p(bits), _p(best_bits), _p(bh), _p(bl),
-                            _p(trace), None if att is None else _p(att), _p(nacc), int(first_sweep))
+                            _p(trace), None if att is None else _p(att), _p(nacc), int(first_sweep),
+                            None if marg is None else _p(marg))
     if rc != 0:
         raise ValueError("anneal: bad arguments")
     vals = [(int(h) << 64) | int(l) for h, l in zip(bh, bl)]
     vals = [v - (1 << 128) if v >= (1 << 127) else v for v in vals]
     best = np.array(vals, dtype=np.int64) if canon.integer else np.array([math.ldexp(float(v), -s) for v in vals])
-    return dict(final_bits=bits, best_bits=best_bits, best_e=best, trace=trace[:sweeps], accepts=int(nacc[0]))
+    out = dict(final_bits=bits, best_bits=best_bits, best_e=best, trace=trace[:sweeps], accepts=int(nacc[0]))
+    if margins:
+        out["margin"] = marg[:, :sweeps]
+    return out

@@ -240,12 +240,18 @@ static inline uint64_t draw(uint64_t seed, uint64_t inst, uint64_t b, uint64_t s
  * visited in that sweep by that group; skipped variables are not drawn for.
  * Outputs: final bits, best bits, exact best energies (fixed point),
  * per-sweep trace of min over replicas of the best energy (double).
+ * Optional margin_out [B][S]: for replica b and sweep s, the smallest over
+ * the sweep's decisions of |dE beta + ln u| / (beta A), where A is the sum of
+ * |w_S| over the monomials S containing i whose other variables are set (so
+ * that |dE| <= A).  The acceptance test is dE beta < -ln u (for dE <= 0 it
+ * always holds), so any evaluation of dE whose error stays below that
+ * fraction of A takes the same decision.  +inf when A = 0 or u = 0.
  * ---------------------------------------------------------------------- */
 int orc_anneal(int n_vars, int n_mono, const int64_t* mono_ptr, const int32_t* mono_idx,
                const int64_t* coeff, int s_scale, int64_t B, int S, const double* temps,
                uint64_t seed, uint64_t inst, int init_given, uint64_t* bits_inout,
                uint64_t* best_bits_out, int64_t* best_hi, uint64_t* best_lo, double* trace_out,
-               const unsigned char* attempt, int64_t* n_accept_out, int s0) {
+               const unsigned char* attempt, int64_t* n_accept_out, int s0, double* margin_out) {
   if (n_vars > 4096) return -1;
   int64_t* cnt = (int64_t*)calloc((size_t)n_vars + 1, sizeof(int64_t));
   for (int m = 0; m < n_mono; ++m)
@@ -274,25 +280,34 @@ int orc_anneal(int n_vars, int n_mono, const int64_t* mono_ptr, const int32_t* m
     memcpy(bx, x, (size_t)n_vars);
     for (int s = 0; s < S; ++s) {
       double beta = 1.0 / temps[s]; /* inverse temperature of this sweep */
+      double mmin = INFINITY;
       for (int i = 0; i < n_vars; ++i) {
         if (attempt && !attempt[((size_t)(b / 16) * (size_t)S + (size_t)s) * (size_t)n_vars + (size_t)i]) continue;
-        i128 g = 0;
+        i128 g = 0, ga = 0;
         for (int64_t a = cnt[i]; a < cnt[i + 1]; ++a) {
           int m = inc[a];
           int on = 1;
           for (int64_t q = mono_ptr[m]; q < mono_ptr[m + 1]; ++q)
             if (mono_idx[q] != i && !x[mono_idx[q]]) { on = 0; break; }
-          if (on) g += (i128)coeff[m];
+          if (on) {
+            g += (i128)coeff[m];
+            ga += (i128)(coeff[m] < 0 ? -coeff[m] : coeff[m]);
+          }
         }
         i128 de = x[i] ? -g : g;
         double ded = fixed_to_double(de, s_scale);
         double u = u01(draw(seed, inst, (uint64_t)b, (uint64_t)(s0 + s), i, 0));
+        if (margin_out && ga != 0 && u > 0.0) {
+          double m = fabs(ded * beta + log(u)) / (beta * fixed_to_double(ga, s_scale));
+          if (m < mmin) mmin = m;
+        }
         if (ded <= 0.0 || u < exp(-ded * beta)) {
           x[i] ^= 1;
           e += de;
           total_acc++;
         }
       }
+      if (margin_out) margin_out[(size_t)b * (size_t)S + (size_t)s] = mmin;
       if (e < best) {
         best = e;
         memcpy(bx, x, (size_t)n_vars);
@@ -336,5 +351,15 @@ int orc_num_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+/* Threads of the following oracle calls (timing on one core or on all). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
 #endif
 }

@@ -401,3 +401,54 @@ def test_anneal_uses_the_schedule_temperature_each_sweep():
         flips = (not up) or u < math.exp(-1.0 / T[s])  # dE = -1 going down is always taken
         assert int(res["final_bits"][0, 0]) == (int(x[0, 0]) ^ int(flips))
         x = res["final_bits"]
+
+
+def _np_philox_word(ctr, key, lane):
+    """Word `lane` of Philox4x64-10 at `ctr`, from numpy's generator (which
+    increments its counter before the first block)."""
+    words = [int(v) for v in ctr]
+    for j in range(4):
+        if words[j] > 0:
+            words[j] -= 1
+            break
+        words[j] = 2 ** 64 - 1
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(words, dtype=np.uint64))
+    return int(g.random_raw(4)[lane])
+
+
+def test_anneal_margins_by_hand():
+    """The oracle's per-sweep decision margins, replayed in plain Python: the
+    flip change from two energy sums (its definition), the acceptance draw
+    from numpy's Philox, A = sum |w| over the active monomials containing the
+    visited bit, margin = |dE beta + ln u| / (beta A) (Sec. II.D.1 acceptance
+    u < exp(-dE beta)); the final states must agree as well."""
+    rng = np.random.default_rng(5)
+    n, B, S, seed = 6, 4, 3, 17
+    monos = [m for r in (1, 2, 3) for m in itertools.combinations(range(n), r)]
+    ws = [float(np.float32(v)) for v in rng.normal(size=len(monos))]
+    terms = W.poly_to_terms(n, W.RawPoly(list(zip(monos, ws))), False)
+    c = _canon(terms)
+    x0 = rng.integers(0, 2, size=(B, n)).astype(np.uint8)
+    res = oracle.anneal(c, B, S, 3.0, 0.3, seed=seed, init_bits=W.pack_bits(x0), margins=True)
+    temps = oracle.schedule(3.0, 0.3, S)
+
+    def energy(x):
+        return math.fsum(w for m, w in zip(monos, ws) if all(x[v] for v in m))
+
+    for b in range(B):
+        x = [int(v) for v in x0[b]]
+        for s in range(S):
+            beta = 1.0 / temps[s]
+            mm = math.inf
+            for i in range(n):
+                y = list(x)
+                y[i] ^= 1
+                de = energy(y) - energy(x)
+                a = math.fsum(abs(w) for m, w in zip(monos, ws) if i in m and all(x[v] for v in m if v != i))
+                u = (_np_philox_word((b, s, i // 4, 0), (seed, 0), i % 4) >> 11) * 2.0 ** -53
+                if a > 0 and u > 0:
+                    mm = min(mm, abs(de * beta + math.log(u)) / (beta * a))
+                if de <= 0 or u < math.exp(-de * beta):
+                    x = y
+            assert res["margin"][b, s] == pytest.approx(mm, rel=1e-9, abs=1e-13)
+        assert W.unpack_bits(res["final_bits"], n)[b].tolist() == x
