@@ -68,13 +68,23 @@ enum { HOBO_COEFF_INT64 = 0, HOBO_COEFF_F64 = 1 };
  *           [-128, 127]; INT8 matrix-core products, int32 per-digit sums,
  *           recombined exactly in int64.  Integer tensors only.
  *  FP64   : double-precision term-by-term sums (hobo_energy only; used to
- *           rescore states) */
+ *           rescore states)
+ *  FP16X2 : coefficient c (rounded to FP32) times a per-tensor power of two
+ *           2^e (the largest |c| 2^e in [2^14, 2^15)) split as
+ *           hi = fp16(c 2^e), lo = fp16(c 2^e - hi); two FP16 matrix-core
+ *           passes at the BF16 rate, FP32 sums multiplied by 2^-e (exact).
+ *           About 22 significant bits per coefficient (error at most
+ *           2^-22 |c|), against 16 for BF16X2, for every |c| above 2^-17
+ *           times the largest |c|; smaller coefficients keep an absolute
+ *           error below 2^-39 times the largest.  Same tile size and speed
+ *           as BF16X2. */
 enum {
   HOBO_PREC_FP32 = 0,
   HOBO_PREC_BF16X2 = 1,
   HOBO_PREC_BF16X3 = 2,
   HOBO_PREC_INT8X4 = 3,
-  HOBO_PREC_FP64 = 4
+  HOBO_PREC_FP64 = 4,
+  HOBO_PREC_FP16X2 = 5
 };
 
 typedef struct hobo_tensor hobo_tensor;
@@ -129,6 +139,23 @@ hobo_status hobo_tensor_monomials(const hobo_tensor* t, int64_t* mono_ptr, int64
  * N^k <= capacity and N^k <= 2^26. */
 hobo_status hobo_tensor_export_dense(const hobo_tensor* t, void* host_out, int64_t capacity);
 
+/* Matrix-core work of one device layout, for measurement: the layout that
+ * hobo_energy (fn 1), hobo_local_fields (fn 2) or hobo_anneal_batch (fn 4,
+ * the blocked layout where it applies, else the per-bit one) uses for
+ * `precision`, created on first use (blocks the host).  issued_flops counts
+ * every 16-column coefficient tile the kernels multiply for one replica
+ * (one evaluation, or one annealing sweep): tiles x 16 columns x K rows
+ * (32, or 64 for INT8X4) x 2 x passes (1 FP32, 2 BF16X2 / FP16X2,
+ * 3 BF16X3, 4 INT8X4 digits); zero entries inside stored tiles count, absent
+ * tiles do not. */
+typedef struct {
+  int64_t chunks;       /* K steps of the layout */
+  int64_t tiles;        /* stored coefficient tiles (the shared zero tile excluded) */
+  int64_t issued_flops; /* matrix-core flops (or int ops) issued per replica */
+  int64_t bytes;        /* device bytes of the layout */
+} hobo_layout_info;
+hobo_status hobo_tensor_layout_info(hobo_tensor* t, int32_t fn, int32_t precision, hobo_layout_info* out);
+
 /* Create the device layouts of `t` for the functions in `fn_mask`
  * (1 = hobo_energy, 2 = hobo_local_fields, 4 = hobo_anneal_batch) and the
  * precisions in `prec_mask` (bit p = precision p).  Blocks the host. */
@@ -138,7 +165,7 @@ hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_
  * the paper's batch contraction (Sec. IV.C) of its HOBO tensor (Sec. II.C).
  *  x_bits    : device uint64 [W][B]
  *  B         : rows, >= 1
- *  precision : FP32 | BF16X2 | BF16X3 | INT8X4 (integer tensors) | FP64
+ *  precision : FP32 | BF16X2 | BF16X3 | FP16X2 | INT8X4 (integer tensors) | FP64
  *  e_out     : device int64[B] for integer tensors, double[B] for real ones
  *  stream    : hipStream_t */
 hobo_status hobo_energy(const hobo_tensor* t, const uint64_t* x_bits, int64_t B,
@@ -148,7 +175,7 @@ hobo_status hobo_energy(const hobo_tensor* t, const uint64_t* x_bits, int64_t B,
  * = (1 - 2 x_{b,i}) g_{b,i}, with the local field
  * g_{b,i} = sum_{S containing i} w_S prod_{j in S, j != i} x_{b,j},
  * the quantity the Metropolis search (Sec. II.D.1) needs for every bit.
- *  precision : FP32 | BF16X2 | BF16X3 | INT8X4 (integer tensors)
+ *  precision : FP32 | BF16X2 | BF16X3 | FP16X2 | INT8X4 (integer tensors)
  *  de_out    : device [B][N] row-major: int64 for integer tensors, float
  *              otherwise
  *  e_out     : optional device energies (as in hobo_energy), computed from
@@ -162,12 +189,12 @@ enum { HOBO_INIT_RANDOM = 0, HOBO_INIT_GIVEN = 1 };
 enum { HOBO_PROPOSAL_METROPOLIS = 0, HOBO_PROPOSAL_MASKED = 1, HOBO_PROPOSAL_LEARNED = 2 };
 enum { HOBO_LAUNCH_PER_INSTANCE = 0, HOBO_LAUNCH_PERSISTENT = 1, HOBO_LAUNCH_GRAPH = 2 };
 /* annealing kernels: AUTO picks BLOCKS where it applies (order <= 3, FP32 /
- * BF16X2 / BF16X3), else SLABS.  Both run the same chain. */
+ * BF16X2 / BF16X3 / FP16X2), else SLABS.  Both run the same chain. */
 enum { HOBO_ANNEAL_AUTO = 0, HOBO_ANNEAL_SLABS = 1, HOBO_ANNEAL_BLOCKS = 2 };
 
 typedef struct {
   int32_t sweeps;      /* sweeps of this call, >= 0 */
-  int32_t precision;   /* FP32 | BF16X2 | BF16X3 | INT8X4 */
+  int32_t precision;   /* FP32 | BF16X2 | BF16X3 | FP16X2 | INT8X4 */
   double t_start;      /* T_0 > 0 */
   double t_end;        /* T_{L-1} > 0; T_s = T_0 (T_end/T_0)^(s/(L-1)), L = schedule length */
   uint64_t seed;

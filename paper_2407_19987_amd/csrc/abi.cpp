@@ -44,7 +44,7 @@ hobo_status need_device() {
   return HOBO_OK;
 }
 
-bool valid_prec(int p) { return p >= HOBO_PREC_FP32 && p <= HOBO_PREC_FP64; }
+bool valid_prec(int p) { return p >= HOBO_PREC_FP32 && p <= HOBO_PREC_FP16X2; }
 
 // Tile shape of the evaluation kernels: 16*rt replicas x 16*ct columns per
 // wave.  Narrower column groups give more waves when B is small.
@@ -353,19 +353,46 @@ hobo_status hobo_tensor_export_dense(const hobo_tensor* t, void* host_out, int64
   return ok();
 }
 
+hobo_status hobo_tensor_layout_info(hobo_tensor* t, int32_t fn, int32_t precision, hobo_layout_info* out) {
+  g_err.clear();
+  if (!t || !out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (fn != 1 && fn != 2 && fn != 4) return fail(HOBO_ERR_INVALID_ARG, "fn must be 1, 2 or 4");
+  if (!hobo::tiled_prec(precision)) return fail(HOBO_ERR_PRECISION, "no tiled layout for this precision");
+  std::string err;
+  if (int s = hobo::check_prec(&t->t, precision, &err)) return fail(s, err);
+  if (t->t.n_mono() == 0) {
+    std::memset(out, 0, sizeof(*out));
+    return ok();
+  }
+  if (hobo_status s = need_device()) return s;
+  int mode = fn == 1 ? hobo::M_ENERGY : fn == 2 ? hobo::M_FIELDS : hobo::M_SLABS;
+  if (fn == 4 && t->t.order <= 3 && precision != HOBO_PREC_INT8X4) mode = hobo::M_BLOCKS;
+  hobo::Packed* pk;
+  if (int s = hobo::get_packed(&t->t, mode, precision, &pk, &err)) return fail(s, err);
+  const int64_t k_rows = precision == HOBO_PREC_INT8X4 ? 64 : 32;
+  const int64_t passes = precision == HOBO_PREC_FP32 ? 1
+                         : precision == HOBO_PREC_BF16X3 ? 3
+                         : precision == HOBO_PREC_INT8X4 ? 4 : 2;
+  out->chunks = pk->nchunks;
+  out->tiles = pk->ntiles > 0 ? pk->ntiles - 1 : 0;
+  out->issued_flops = out->tiles * 16 * k_rows * 2 * passes;
+  out->bytes = (int64_t)pk->bytes;
+  return ok();
+}
+
 hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_mask) {
   g_err.clear();
   if (!t) return fail(HOBO_ERR_INVALID_ARG, "tensor is NULL");
   if (fn_mask & ~7u) return fail(HOBO_ERR_INVALID_ARG, "unknown function bits");
-  if (prec_mask & ~31u) return fail(HOBO_ERR_INVALID_ARG, "unknown precision bits");
-  for (int p = 0; p < HOBO_PREC_FP64; ++p) {
+  if (prec_mask & ~63u) return fail(HOBO_ERR_INVALID_ARG, "unknown precision bits");
+  for (int p = 0; p <= HOBO_PREC_FP16X2; ++p) {
     std::string e;
-    if ((prec_mask & (1u << p)) && fn_mask)
+    if ((prec_mask & (1u << p)) && fn_mask && p != HOBO_PREC_FP64)
       if (int s = hobo::check_prec(&t->t, p, &e)) return fail(s, e);
   }
   if (hobo_status s = need_device()) return s;
   std::string err;
-  for (int p = 0; p <= HOBO_PREC_FP64; ++p) {
+  for (int p = 0; p <= HOBO_PREC_FP16X2; ++p) {
     if (!(prec_mask & (1u << p))) continue;
     if (p == HOBO_PREC_INT8X4 && !t->t.integer) return fail(HOBO_ERR_PRECISION, "INT8X4 needs an integer tensor");
     if (p == HOBO_PREC_FP64) {
@@ -438,7 +465,7 @@ hobo_status hobo_local_fields(const hobo_tensor* tc, const uint64_t* x_bits, int
   if (hobo_status s = check_bits_args(tc, x_bits, B, precision)) return s;
   if (!de_out) return fail(HOBO_ERR_INVALID_ARG, "de_out is NULL");
   if (precision == HOBO_PREC_FP64)
-    return fail(HOBO_ERR_PRECISION, "hobo_local_fields supports FP32, BF16X2, BF16X3 and INT8X4");
+    return fail(HOBO_ERR_PRECISION, "hobo_local_fields supports FP32, BF16X2, BF16X3, FP16X2 and INT8X4");
   if (hobo_status s = need_device()) return s;
   hobo_tensor* t = const_cast<hobo_tensor*>(tc);
   std::string err;
@@ -495,8 +522,8 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     if (!(P.p_floor >= 0.0f && P.p_floor <= 1.0f)) return fail(HOBO_ERR_INVALID_ARG, "p_floor must be in [0, 1]");
     if (std::isnan(P.tau)) return fail(HOBO_ERR_INVALID_ARG, "tau is NaN");
   }
-  if (P.precision < HOBO_PREC_FP32 || P.precision > HOBO_PREC_INT8X4)
-    return fail(HOBO_ERR_PRECISION, "annealing precision must be FP32, BF16X2, BF16X3 or INT8X4");
+  if (!hobo::tiled_prec(P.precision))
+    return fail(HOBO_ERR_PRECISION, "annealing precision must be FP32, BF16X2, BF16X3, FP16X2 or INT8X4");
   if (launch_mode < HOBO_LAUNCH_PER_INSTANCE || launch_mode > HOBO_LAUNCH_GRAPH)
     return fail(HOBO_ERR_INVALID_ARG, "unknown launch_mode");
   if (P.waves_per_block != 0 && P.waves_per_block != 1 && P.waves_per_block != 2 && P.waves_per_block != 4 &&
@@ -609,12 +636,28 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     beta[(size_t)s] = 1.0 / T;
   }
   const int init_random = P.init == HOBO_INIT_RANDOM ? 1 : 0;
+  // Tuned annealer width of the call's kernel of each kind (1 blocked, 0
+  // per-bit): the hobo_autotune result of its costliest instance (stored
+  // tiles x replicas), 0 if that one was not tuned.  All instances of a kind
+  // share one persistent launch, so the instance that dominates its time
+  // decides its shape.
+  auto tuned_of_kind = [&](int kind) {
+    int best = -1;
+    int64_t best_cost = -1;
+    for (int j = 0; j < n_instances; ++j) {
+      if (blocked[(size_t)j] != kind) continue;
+      const int64_t c = (int64_t)pks[(size_t)j]->ntiles * replicas[j];
+      if (c > best_cost) {
+        best_cost = c;
+        best = j;
+      }
+    }
+    return best < 0 ? 0 : tuned_shape(tensors[best]->t, hobo::TK_ANNEAL, P.precision, replicas[best]);
+  };
+  const int tuned_blk = tuned_of_kind(1);
   // waves per work-group of the per-bit slab kernel: requested, tuned, or its default
   // (at most 8: a request of 16 means the widest)
-  const int slab_waves = std::min(8, P.waves_per_block ? P.waves_per_block
-                                     : (n_instances == 1 ? tuned_shape(tensors[0]->t, hobo::TK_ANNEAL,
-                                                                       P.precision, replicas[0])
-                                                         : 0));
+  const int slab_waves = std::min(8, P.waves_per_block ? P.waves_per_block : tuned_of_kind(0));
   auto base_plan = [&]() {
     hobo::AnnealPlan pl;
     pl.sweeps = S;
@@ -632,7 +675,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   // sixteen (its eight-wave form runs short of registers)
   auto blk_waves = [&](int64_t tiles) {
     int nw = P.waves_per_block;
-    if (!nw && n_instances == 1) nw = tuned_shape(tensors[0]->t, hobo::TK_ANNEAL, P.precision, replicas[0]);
+    if (!nw) nw = tuned_blk;
     if (!nw) nw = (tiles <= 256 || P.precision == HOBO_PREC_BF16X3) ? 16 : 8;
     return nw < 2 ? 2 : nw;
   };
@@ -657,6 +700,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     for (auto v : pbits) key.push_back(v);
   }
   key.push_back((uint64_t)(uintptr_t)P.attempt);
+  key.push_back(((uint64_t)(uint32_t)slab_waves << 32) | (uint32_t)tuned_blk);  // tuned shapes in force
   if (learned) {
     uint64_t lb[2];
     uint32_t tb32, pf32;
@@ -717,6 +761,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
       d.blocks = pk->d_blocks;
       d.triples = pk->d_triples;
       d.nblocks = pk->nblocks;
+      d.inv_scale = std::ldexp(1.0, -pk->scale_exp);
       if (blocked[(size_t)j]) {
         d.unif = reinterpret_cast<double*>(wb + off_unif + unif_off);
         unif_off += (size_t)nt * (size_t)pk->nblocks * 2048 * (size_t)unif_sweeps;

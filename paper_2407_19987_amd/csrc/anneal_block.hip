@@ -114,13 +114,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
   constexpr int NBUF = STAGER ? 2 : 1;           // buffers of the staged table and uniforms
   constexpr int D = kRing;
   constexpr int RPC = PT<P>::RPC;
-  constexpr int TB = P == P_FP32 ? 2048 : (P == P_BF16X2 ? 2048 : 3072);
+  constexpr int TB = P == P_BF16X3 ? 3072 : 2048;
+  // FP16X2 tiles and tables hold the coefficients times 2^scale_exp
+  constexpr bool SCALED = P == P_FP16X2;
   static_assert(D == kBlockRing, "the schedule is built in rounds of the ring depth");
   __shared__ unsigned long long sbits[64];  // 16 replicas x 32 bytes
   // the same bits byte-transposed, [byte][replica]: the streaming waves' reads
   // of one byte position for 16 replicas fall in 4 consecutive banks
   __shared__ __attribute__((aligned(16))) unsigned char sbT[32][16];
-  // nibble -> four BF16 values 0 / 1.0 (16 entries x 8 bytes: every entry in
+  // nibble -> four BF16 (FP16) values 0 / 1.0 (16 entries x 8 bytes: every entry in
   // its own two banks, so the operand reads never conflict)
   __shared__ unsigned long long sNib[16];
   __shared__ unsigned long long sbest[64];
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
 
   for (int n = threadIdx.x; n < 16; n += blockDim.x) {
     unsigned long long v = 0;
-    for (int i = 0; i < 4; ++i) v |= (unsigned long long)(((n >> i) & 1) ? 0x3F80u : 0u) << (16 * i);
+    for (int i = 0; i < 4; ++i) v |= (unsigned long long)(((n >> i) & 1) ? one16<P>() : 0u) << (16 * i);
     sNib[n] = v;
   }
   for (int e = threadIdx.x; e < 128; e += blockDim.x) {
@@ -301,7 +303,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
           stage_uniforms(cs, q, 0);
           drain();
         }
-        const double beta = gld(p.beta + (cs - p.s_first));
+        // in the scaled units of FP16X2 flip changes the inverse temperature
+        // carries the factor 2^-scale_exp (exact), so the test is unchanged
+        const double beta = SCALED ? gld(p.beta + (cs - p.s_first)) * I.inv_scale : gld(p.beta + (cs - p.s_first));
         lds_barrier();  // A
         // ---- sixteen sequential decisions, sub-lane s holding bits s, s+4, s+8, s+12
         float gq[4];
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
           const float dEo = __int_as_float(quad_bcast(__float_as_int(dE), c & 3));
           if (tk) {
             xb ^= 1u << c;
-            E += (double)dEo;
+            E += SCALED ? (double)dEo * I.inv_scale : (double)dEo;
           }
           if (__builtin_amdgcn_ballot_w64(tk != 0)) {  // any flip among the 16 replicas
             const float dl = tk ? (xc ? -1.0f : 1.0f) : 0.0f;
@@ -567,23 +571,37 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
   }
 }
 
+// one precision's launcher (each defined in the build of that precision)
+template <int P> int launch_anneal_block_p(const AnnealParams& ap, int nw, int nblk, hipStream_t st);
+
 template <int P, int NW>
 static void launch_block_t(const AnnealParams& ap, int nblk, hipStream_t st) {
   TimedLaunch tl(0, st);
   hipLaunchKernelGGL((anneal_block_kernel<P, NW>), dim3((unsigned)nblk), dim3(64 * NW), 0, st, ap);
 }
 
-int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipStream_t st) {
-#define HOBO_AB(PV, NWV)                     \
-  if (prec == PV && nw == NWV) {             \
-    launch_block_t<PV, NWV>(ap, nblk, st);   \
-    return 0;                                \
+#ifdef HOBO_BLOCK_PREC
+// this translation unit instantiates one precision's kernels (the file is
+// compiled once per precision of the blocked annealer, so they build in parallel)
+template <>
+int launch_anneal_block_p<HOBO_BLOCK_PREC>(const AnnealParams& ap, int nw, int nblk, hipStream_t st) {
+  switch (nw) {
+    case 2: launch_block_t<HOBO_BLOCK_PREC, 2>(ap, nblk, st); return 0;
+    case 4: launch_block_t<HOBO_BLOCK_PREC, 4>(ap, nblk, st); return 0;
+    case 8: launch_block_t<HOBO_BLOCK_PREC, 8>(ap, nblk, st); return 0;
+    case 16: launch_block_t<HOBO_BLOCK_PREC, 16>(ap, nblk, st); return 0;
+    default: return -1;
   }
-  HOBO_AB(P_FP32, 2) HOBO_AB(P_FP32, 4) HOBO_AB(P_FP32, 8) HOBO_AB(P_FP32, 16)
-  HOBO_AB(P_BF16X2, 2) HOBO_AB(P_BF16X2, 4) HOBO_AB(P_BF16X2, 8) HOBO_AB(P_BF16X2, 16)
-  HOBO_AB(P_BF16X3, 2) HOBO_AB(P_BF16X3, 4) HOBO_AB(P_BF16X3, 8) HOBO_AB(P_BF16X3, 16)
-#undef HOBO_AB
-  return -1;
+}
+#else
+int launch_anneal_block(const AnnealParams& ap, int prec, int nw, int nblk, hipStream_t st) {
+  switch (prec) {
+    case P_FP32: return launch_anneal_block_p<P_FP32>(ap, nw, nblk, st);
+    case P_BF16X2: return launch_anneal_block_p<P_BF16X2>(ap, nw, nblk, st);
+    case P_BF16X3: return launch_anneal_block_p<P_BF16X3>(ap, nw, nblk, st);
+    case P_FP16X2: return launch_anneal_block_p<P_FP16X2>(ap, nw, nblk, st);
+    default: return -1;
+  }
 }
 
 // -log(u) of every (replica, sweep, bit) of a blocked launch window, one
@@ -624,5 +642,6 @@ void launch_anneal_uniforms(const AnnealParams& ap, hipStream_t st) {
 
 int anneal_mask_window() { return kMaskWin; }
 int anneal_sweep_window() { return kSweepWin; }
+#endif  // HOBO_BLOCK_PREC
 
 }  // namespace hobo

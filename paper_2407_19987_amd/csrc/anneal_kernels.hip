@@ -59,14 +59,14 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
   __shared__ ChunkMeta smeta[2][2 * kMetaBlock];
   __shared__ double strace[kTraceEpoch];
   __shared__ double sbeta[kTraceEpoch];
-  build_luts(&L);
+  build_luts<P>(&L);
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   const bool owner = j < 4;
   const int orow = 4 * g + j;
   unsigned char* myb = reinterpret_cast<unsigned char*>(sbits[w]);
-  const int tb = (P == P_FP32) ? 2048 : (P == P_BF16X2 ? 2048 : (P == P_BF16X3 ? 3072 : 4096));
+  const int tb = (P == P_FP32 || P == P_BF16X2 || P == P_FP16X2) ? 2048 : (P == P_BF16X3 ? 3072 : 4096);
   int buf = 0;
 
   for (int it = blockIdx.x; it < p.n_items; it += gridDim.x) {
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int col = 16 * t + j;
-            v[r] = (col < N && bit_at(myb + (4 * g + r) * 32, col)) ? acc_f<P>(acc[k], r) : 0.0;
+            v[r] = (col < N && bit_at(myb + (4 * g + r) * 32, col)) ? acc_f<P>(acc[k], r, I.inv_scale) : 0.0;
           }
           const double rs = rowsum4(v[0], v[1], v[2], v[3], j);
           if ((j & 3) == 0) spart[buf][t][4 * g + (j >> 2)] = rs;
@@ -302,6 +302,7 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
   }
 }
 
+#ifndef HOBO_SLAB_PREC
 // ------------------------------------------------------------ multi-instance helpers
 // grid.y = instance; x covers replicas (and words for init)
 __global__ void init_random_multi(const InstSmall* in, unsigned long long seed) {
@@ -382,14 +383,23 @@ __global__ void trace_reduce_multi(const InstSmall* in, int S) {
   I.trace_out[s] = v;
 }
 
+#endif  // !HOBO_SLAB_PREC
+
 template <int P, int CTW, int CS>
 static void launch_anneal_t(const AnnealParams& ap, int nblk, hipStream_t st) {
   TimedLaunch tl(0, st);
   hipLaunchKernelGGL((anneal_kernel<P, CTW, CS>), dim3((unsigned)nblk), dim3(64 * CS), 0, st, ap);
 }
 
-template <int P>
-static int dispatch_anneal(const AnnealParams& ap, int ctw, int cs, int nblk, hipStream_t st) {
+// one precision's shape dispatch (each defined in the build of that precision)
+template <int P> int dispatch_anneal_prec(const AnnealParams& ap, int ctw, int cs, int nblk, hipStream_t st);
+
+#ifdef HOBO_SLAB_PREC
+// this translation unit instantiates one precision's per-bit kernels (the
+// file is compiled once per precision, so they build in parallel)
+template <>
+int dispatch_anneal_prec<HOBO_SLAB_PREC>(const AnnealParams& ap, int ctw, int cs, int nblk, hipStream_t st) {
+  constexpr int P = HOBO_SLAB_PREC;
 #define HOBO_AN(CTWV, CSV)                          \
   if (ctw == CTWV && cs == CSV) {                   \
     launch_anneal_t<P, CTWV, CSV>(ap, nblk, st);    \
@@ -403,6 +413,7 @@ static int dispatch_anneal(const AnnealParams& ap, int ctw, int cs, int nblk, hi
   return -1;
 }
 
+#else
 void anneal_shape(int T, int cs_req, int* ctw, int* cs) {
   int c = cs_req;
   // default: one wave per column tile, up to eight waves (deepest rings)
@@ -490,10 +501,11 @@ int enqueue_anneal_sweeps(const AnnealTables& tb, const AnnealPlan& pl, int s_be
     const int nblk = pl.n_slab < 2048 ? pl.n_slab : 2048;  // one work-group per 16 replicas, persistent beyond
     int r = -1;
     switch (pl.prec) {
-      case P_FP32: r = dispatch_anneal<P_FP32>(ap, pl.ct, pl.nw, nblk, st); break;
-      case P_BF16X2: r = dispatch_anneal<P_BF16X2>(ap, pl.ct, pl.nw, nblk, st); break;
-      case P_BF16X3: r = dispatch_anneal<P_BF16X3>(ap, pl.ct, pl.nw, nblk, st); break;
-      case P_INT8X4: r = dispatch_anneal<P_INT8X4>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_FP32: r = dispatch_anneal_prec<P_FP32>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_BF16X2: r = dispatch_anneal_prec<P_BF16X2>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_BF16X3: r = dispatch_anneal_prec<P_BF16X3>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_FP16X2: r = dispatch_anneal_prec<P_FP16X2>(ap, pl.ct, pl.nw, nblk, st); break;
+      case P_INT8X4: r = dispatch_anneal_prec<P_INT8X4>(ap, pl.ct, pl.nw, nblk, st); break;
       default: break;
     }
     if (r != 0) {
@@ -525,5 +537,7 @@ int enqueue_anneal_seq(const AnnealTables& tb, const AnnealPlan& pl, void* strea
     return s;
   return enqueue_anneal_finish(tb, pl, stream, err);
 }
+
+#endif  // HOBO_SLAB_PREC
 
 }  // namespace hobo

@@ -27,6 +27,7 @@
 namespace hobo {
 
 typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -47,6 +48,7 @@ template <> struct PT<P_FP32> { static constexpr int RPC = 4, NP = 1, NLD = 2; }
 template <> struct PT<P_BF16X2> { static constexpr int RPC = 4, NP = 2, NLD = 2; };
 template <> struct PT<P_BF16X3> { static constexpr int RPC = 4, NP = 3, NLD = 3; };
 template <> struct PT<P_INT8X4> { static constexpr int RPC = 8, NP = 4, NLD = 4; };
+template <> struct PT<P_FP16X2> { static constexpr int RPC = 4, NP = 2, NLD = 2; };
 
 // per-tile B registers: NLD x 16 bytes per lane
 template <int P> struct BTile { u4 v[PT<P>::NLD]; };
@@ -60,16 +62,21 @@ template <int P> struct AOp { u4 v; };  // bf16x8 / 16 int8 / (FP32: low byte = 
 
 // ------------------------------------------------------------ LDS tables
 struct Luts {
-  u4 bf16[256];         // byte -> eight BF16 values 0 / 1.0
+  u4 bf16[256];         // byte -> eight 16-bit values 0 / 1.0 (BF16, or FP16 for FP16X2)
   unsigned long long i8[256];  // byte -> eight INT8 values 0 / 1
 };
 
+// the 16-bit pattern of 1.0 in the operand type of precision P
+template <int P> constexpr unsigned one16() { return P == P_FP16X2 ? 0x3C00u : 0x3F80u; }
+
+template <int P = P_BF16X2>
 __device__ inline void build_luts(Luts* L) {
+  constexpr unsigned one = one16<P>();
   for (int m = threadIdx.x; m < 256; m += blockDim.x) {
     u4 v;
     for (int d = 0; d < 4; ++d) {
       unsigned lo = (m >> (2 * d)) & 1u, hi = (m >> (2 * d + 1)) & 1u;
-      v[d] = (lo ? 0x3F80u : 0u) | (hi ? 0x3F800000u : 0u);
+      v[d] = (lo ? one : 0u) | (hi ? one << 16 : 0u);
     }
     L->bf16[m] = v;
     unsigned long long b = 0;
@@ -134,6 +141,10 @@ __device__ inline void mma(AccT<P>& c, const AOp<P>& a, const BTile<P>& b) {
     i4 av = __builtin_bit_cast(i4, a.v);
     for (int q = 0; q < 4; ++q)
       c.v[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, __builtin_bit_cast(i4, b.v[q]), c.v[q], 0, 0, 0);
+  } else if constexpr (P == P_FP16X2) {
+    f16x8 av = __builtin_bit_cast(f16x8, a.v);
+    for (int q = 0; q < 2; ++q)
+      c.v = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, __builtin_bit_cast(f16x8, b.v[q]), c.v, 0, 0, 0);
   } else {
     bf16x8 av = __builtin_bit_cast(bf16x8, a.v);
     for (int q = 0; q < PT<P>::NP; ++q)
@@ -149,20 +160,26 @@ template <int P> __device__ inline void acc_zero(AccT<P>& c) {
   }
 }
 
-// value r (0..3) of an accumulator as double (exact for INT8 limbs up to 2^53)
-template <int P> __device__ inline double acc_f(const AccT<P>& c, int r) {
+// value r (0..3) of an accumulator as double (exact for INT8 limbs up to 2^53);
+// FP16X2 sums are of coefficients times 2^scale_exp and are multiplied by
+// scl = 2^-scale_exp (exact), the other precisions ignore scl
+template <int P> __device__ inline double acc_f(const AccT<P>& c, int r, double scl = 1.0) {
   if constexpr (P == P_INT8X4) {
     long long v = (long long)c.v[0][r] + ((long long)c.v[1][r] << 8) + ((long long)c.v[2][r] << 16) +
                   ((long long)c.v[3][r] << 24);
     return (double)v;
+  } else if constexpr (P == P_FP16X2) {
+    return (double)c.v[r] * scl;
   } else {
     return (double)c.v[r];
   }
 }
-template <int P> __device__ inline long long acc_i(const AccT<P>& c, int r) {
+template <int P> __device__ inline long long acc_i(const AccT<P>& c, int r, double scl = 1.0) {
   if constexpr (P == P_INT8X4) {
     return (long long)c.v[0][r] + ((long long)c.v[1][r] << 8) + ((long long)c.v[2][r] << 16) +
            ((long long)c.v[3][r] << 24);
+  } else if constexpr (P == P_FP16X2) {
+    return (long long)__builtin_rint((double)c.v[r] * scl);
   } else {
     return (long long)__builtin_rintf(c.v[r]);
   }

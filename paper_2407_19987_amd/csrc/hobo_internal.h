@@ -20,7 +20,9 @@ constexpr int kRunWidth = 8;       // variables per run (one byte of bits)
 constexpr int kTileCols = 16;      // MFMA 16x16 output tile width
 
 // precision modes (values match the public header)
-enum Prec : int { P_FP32 = 0, P_BF16X2 = 1, P_BF16X3 = 2, P_INT8X4 = 3, P_FP64 = 4 };
+enum Prec : int { P_FP32 = 0, P_BF16X2 = 1, P_BF16X3 = 2, P_INT8X4 = 3, P_FP64 = 4, P_FP16X2 = 5 };
+// the precisions with tiled matrix-core layouts
+inline bool tiled_prec(int p) { return (p >= P_FP32 && p <= P_INT8X4) || p == P_FP16X2; }
 
 // layouts a coefficient matrix can be packed for
 enum Mode : int { M_FIELDS = 0, M_ENERGY = 1, M_SLABS = 2, M_BLOCKS = 3 };
@@ -34,6 +36,7 @@ inline int tile_bytes(int prec) {
     case P_FP32: return 64 * 8 * 4;
     case P_BF16X2: return 2 * 64 * 8 * 2;
     case P_BF16X3: return 3 * 64 * 8 * 2;
+    case P_FP16X2: return 2 * 64 * 8 * 2;
     case P_INT8X4: return 4 * 64 * 16;
     default: return 0;
   }
@@ -118,6 +121,11 @@ struct Packed {
   BlockMeta* d_blocks = nullptr;  // blocks mode only, [nblocks]
   float* d_triples = nullptr;     // blocks mode only, [nblocks][16][16][16] w_{abc} at [c][a][b]
   int nblocks = 0;
+  // FP16X2: the tiles (and the blocked layout's order-3 table) hold every
+  // coefficient times 2^scale_exp, so that the largest one sits just below
+  // 2^15 and the FP16 pair keeps 22 significant bits over the whole range;
+  // the kernels multiply their sums by 2^-scale_exp (exact).  0 otherwise.
+  int scale_exp = 0;
   std::vector<BlockMeta> h_blocks;  // blocks mode only
   std::map<int, std::unique_ptr<BlockSchedule>> sched;  // blocks mode: key = nw * 2 + masked
   std::vector<ChunkMeta> h_chunks;
@@ -258,6 +266,7 @@ struct AnnealInstDev {       // per-instance view of the annealing kernel
   unsigned long long inst_id;
   unsigned n_tiles;            // tiles stored in the packed buffer
   unsigned pad2;
+  double inv_scale;            // 2^-scale_exp of the packed layout (1 unless FP16X2)
   const BlockMeta* blocks;     // blocked layout: [nblocks]
   const float* triples;        // blocked layout: [nblocks][16][16][16]
   const uint32_t* sched;       // blocked layout: slot words of the launch's group width

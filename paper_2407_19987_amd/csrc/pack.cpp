@@ -165,7 +165,7 @@ struct PackOut {
 // tiles in precision `prec`.  When `segments` is set the runs of each degree
 // start a new chunk and the chunk that closes a degree carries seg_end.
 int pack_runs(const RunMat& rm, const std::vector<int>& ord, int prec, bool segments, int n_col_tiles,
-              PackOut* po, std::string* err, bool all_tiles = false) {
+              PackOut* po, std::string* err, bool all_tiles = false, int scale_exp = 0) {
   const int rpc = runs_per_chunk(prec);
   const int n = rm.n;
   // padded run sequence (-1 = null run) and per-run order of its degree
@@ -259,6 +259,25 @@ int pack_runs(const RunMat& rm, const std::vector<int>& ord, int prec, bool segm
               dst[e] = h[q];
             }
           }
+        } else if (prec == P_FP16X2) {
+          // c 2^scale_exp as hi = fp16(c'), lo = fp16(c' - hi); c' - hi is
+          // exact in FP32, so the pair carries 22 significant bits
+          int run = seq[(size_t)c * rpc + g];
+          for (int e = 0; e < 8; ++e) {
+            double w = rm.integer ? (double)coef_i(run, e, col) : coef_f(run, e, col);
+            const float f = std::ldexp((float)w, scale_exp);
+            const _Float16 h0 = (_Float16)f;
+            const _Float16 h1 = (_Float16)(f - (float)h0);
+            if (rm.integer && std::ldexp((double)h0 + (double)h1, -scale_exp) != w) {
+              *err = "integer coefficient " + std::to_string((long long)w) + " is not exact in the FP16 split";
+              return HOBO_ERR_RANGE;
+            }
+            uint16_t b0, b1;
+            std::memcpy(&b0, &h0, 2);
+            std::memcpy(&b1, &h1, 2);
+            reinterpret_cast<uint16_t*>(tile + l * 16)[e] = b0;
+            reinterpret_cast<uint16_t*>(tile + 1024 + l * 16)[e] = b1;
+          }
         } else {  // INT8X4
           for (int e = 0; e < 16; ++e) {
             int run = seq[(size_t)c * rpc + 2 * g + (e >> 3)];
@@ -293,6 +312,17 @@ int upload(const std::vector<T>& v, T** dst, size_t* bytes, std::string* err) {
   return HOBO_OK;
 }
 
+// FP16X2 scale: the largest |w| times 2^e lies in [2^14, 2^15), well inside
+// FP16's range (65504) with hi rounding included
+int fp16_scale_exp(const Tensor* t) {
+  double mx = 0.0;
+  for (double w : t->w_f) mx = std::max(mx, std::fabs((double)(float)w));
+  if (!(mx > 0.0)) return 0;
+  int ex;
+  (void)std::frexp(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+  return 15 - ex;
+}
+
 }  // namespace
 
 int check_prec(const Tensor* t, int prec, std::string* err) {
@@ -323,7 +353,7 @@ int check_prec(const Tensor* t, int prec, std::string* err) {
       return HOBO_ERR_RANGE;
     }
   }
-  if (t->integer && (prec == P_FP32 || prec == P_BF16X2 || prec == P_BF16X3)) {
+  if (t->integer && (prec == P_FP32 || prec == P_BF16X2 || prec == P_BF16X3 || prec == P_FP16X2)) {
     // every partial sum of an FP32 accumulation must be an exact integer
     if (t->abs_sum >= ((unsigned __int128)1 << 24)) {
       *err = "integer tensor with sum |w| >= 2^24 cannot be exact in FP32 accumulation; use INT8X4";
@@ -350,6 +380,8 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
   pk->mode = mode;
   pk->prec = prec;
   pk->n_col_tiles = n_col_tiles;
+  if (prec == P_FP16X2) pk->scale_exp = fp16_scale_exp(t);
+  const int sx = pk->scale_exp;
   PackOut po;
   // tile 0 is all zeros: the kernels load it in place of absent tiles so that
   // every chunk issues the same number of loads
@@ -375,7 +407,7 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
         scatter(rm, s, len - 1, s[len - 1], wf, wi);
       }
     }
-    st = pack_runs(rm, run_order(rm), prec, mode == M_FIELDS, n_col_tiles, &po, err);
+    st = pack_runs(rm, run_order(rm), prec, mode == M_FIELDS, n_col_tiles, &po, err, false, sx);
     if (st) return st;
     pk->nchunks = (int)po.chunks.size();
   } else if (mode == M_BLOCKS) {
@@ -438,7 +470,8 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
           const int v3[3] = {s[0] - j0, s[1] - j0, s[2] - j0};
           const int pm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
           for (auto& o : pm)
-            tri[(size_t)q * 4096 + (size_t)v3[o[0]] * 256 + (size_t)v3[o[1]] * 16 + (size_t)v3[o[2]]] = (float)wf;
+            tri[(size_t)q * 4096 + (size_t)v3[o[0]] * 256 + (size_t)v3[o[1]] * 16 + (size_t)v3[o[2]]] =
+                std::ldexp((float)wf, sx);
         }
       }
       BlockMeta& b = bm[(size_t)q];
@@ -465,17 +498,17 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
           std::vector<int> early, late;
           for (int r : run_order(rg)) (reads_prev(rg.desc[(size_t)r]) ? late : early).push_back(r);
           if (!early.empty()) {
-            st = pack_runs(rg, early, prec, false, 1, &po, err, true);
+            st = pack_runs(rg, early, prec, false, 1, &po, err, true, sx);
             if (st) return st;
           }
           b.nearly = (uint32_t)po.chunks.size() - b.chunk0[0];
           if (!late.empty()) {
-            st = pack_runs(rg, late, prec, false, 1, &po, err, true);
+            st = pack_runs(rg, late, prec, false, 1, &po, err, true, sx);
             if (st) return st;
           }
         } else if (li - 1 < npt) {
           RunMat& r = rh[(size_t)(li - 1)];
-          st = pack_runs(r, run_order(r), prec, false, 1, &po, err, true);
+          st = pack_runs(r, run_order(r), prec, false, 1, &po, err, true, sx);
           if (st) return st;
         }
         b.nchunks[li] = (uint32_t)po.chunks.size() - b.chunk0[li];
@@ -518,7 +551,7 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
       }
       sm.chunk0 = (uint32_t)po.chunks.size();
       sm.run0 = (uint32_t)po.runs.size();
-      st = pack_runs(rm, run_order(rm), prec, false, n_col_tiles, &po, err);
+      st = pack_runs(rm, run_order(rm), prec, false, n_col_tiles, &po, err, false, sx);
       if (st) return st;
       sm.nchunks = (uint32_t)po.chunks.size() - sm.chunk0;
       if (sm.nchunks == 0) {  // the annealer visits every slab through at least one chunk

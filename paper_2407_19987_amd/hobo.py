@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(HERE, "libhobo.so")
 # status codes
 OK, ERR_INVALID_ARG, ERR_ORDER, ERR_RANGE, ERR_PRECISION, ERR_NO_DEVICE, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = range(9)
 COEFF_INT64, COEFF_F64 = 0, 1
-PREC_FP32, PREC_BF16X2, PREC_BF16X3, PREC_INT8X4, PREC_FP64 = range(5)
-PREC_NAMES = {"fp32": PREC_FP32, "bf16x2": PREC_BF16X2, "bf16x3": PREC_BF16X3, "int8x4": PREC_INT8X4, "fp64": PREC_FP64}
+PREC_FP32, PREC_BF16X2, PREC_BF16X3, PREC_INT8X4, PREC_FP64, PREC_FP16X2 = range(6)
+PREC_NAMES = {"fp32": PREC_FP32, "bf16x2": PREC_BF16X2, "bf16x3": PREC_BF16X3, "int8x4": PREC_INT8X4,
+              "fp64": PREC_FP64, "fp16x2": PREC_FP16X2}
 INIT_RANDOM, INIT_GIVEN = 0, 1
 PROPOSAL_METROPOLIS, PROPOSAL_MASKED, PROPOSAL_LEARNED = 0, 1, 2
 ANNEAL_AUTO, ANNEAL_SLABS, ANNEAL_BLOCKS = 0, 1, 2
@@ -34,6 +35,7 @@ EXPORTS = [
     "hobo_tensor_export_dense", "hobo_tensor_prepare", "hobo_energy", "hobo_local_fields",
     "hobo_anneal_batch", "hobo_timing_enable", "hobo_timing_read", "hobo_last_error", "hobo_version",
     "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features", "hobo_autotune",
+    "hobo_tensor_layout_info",
 ]
 
 
@@ -47,6 +49,11 @@ class TensorInfo(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("order", ctypes.c_int32), ("is_integer", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("n_monomials", ctypes.c_int64), ("n_per_order", ctypes.c_int64 * 8),
                 ("offset_i64", ctypes.c_int64), ("offset_f64", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+class LayoutInfo(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_int64), ("tiles", ctypes.c_int64), ("issued_flops", ctypes.c_int64),
+                ("bytes", ctypes.c_int64)]
 
 
 class AnnealParams(ctypes.Structure):
@@ -75,6 +82,7 @@ def _load():
     lib.hobo_tensor_monomials.argtypes = [P, P, i64, P, i64, P, i64]
     lib.hobo_tensor_export_dense.argtypes = [P, P, i64]
     lib.hobo_tensor_prepare.argtypes = [P, u32, u32]
+    lib.hobo_tensor_layout_info.argtypes = [P, i32, i32, ctypes.POINTER(LayoutInfo)]
     lib.hobo_energy.argtypes = [P, P, i64, i32, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
@@ -161,6 +169,11 @@ class Tensor:
 
     def prepare(self, fn_mask: int, prec_mask: int):
         _check(lib.hobo_tensor_prepare(self._h, fn_mask, prec_mask))
+
+    def layout_info(self, fn: int, precision: int) -> LayoutInfo:
+        inf = LayoutInfo()
+        _check(lib.hobo_tensor_layout_info(self._h, int(fn), int(precision), ctypes.byref(inf)))
+        return inf
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

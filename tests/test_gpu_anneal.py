@@ -79,8 +79,8 @@ def _int_instance(seed, n, k, lo=-5, hi=5, dens=0.7):
 SLABS, BLOCKS = 1, 2
 
 
-@pytest.mark.parametrize("prec,algo", [(0, SLABS), (1, SLABS), (2, SLABS), (3, SLABS), (0, BLOCKS), (1, BLOCKS),
-                                       (2, BLOCKS)])
+@pytest.mark.parametrize("prec,algo", [(0, SLABS), (1, SLABS), (2, SLABS), (3, SLABS), (5, SLABS), (0, BLOCKS),
+                                       (1, BLOCKS), (2, BLOCKS), (5, BLOCKS)])
 def test_trajectory_identity_int3(env, prec, algo):
     hobo, _ = env
     terms = W.cfg_int3(seed=4)
@@ -262,17 +262,23 @@ def test_real_instance_rescored_energies(env, prec):
     assert g["trace"][-1] <= g["trace"][0]
 
 
-def test_real3_full_size_blocked_anneal(env):
+@pytest.mark.parametrize("prec", [5, 1])
+def test_real3_full_size_blocked_anneal(env, prec):
     """The annealing workload at full size in the benchmark's launch shape
-    (N=128 order 3, 4096 replicas, 1000 sweeps, BF16X2, sixteen-wave blocked
-    groups).  Every reported best energy is the FP64 energy of the reported
-    best state, the trace never rises, and the first 16 replicas reach the
-    oracle's best energies up to near-tie divergence."""
+    (N=128 order 3, 4096 replicas, 1000 sweeps, FP16X2 / BF16X2, sixteen-wave
+    blocked groups).  Every reported best energy is the FP64 energy of the
+    reported best state, the trace never rises, the tracked best energy of the
+    best replica has drifted from its FP64 energy by less than 1e-5 of it (the
+    tracked energy adds up every accepted flip change), and the first 16
+    replicas reach the oracle's best energies up to near-tie divergence."""
     hobo, _ = env
     terms = W.cfg_real3(seed=0)
     c = oracle.canonicalize(terms)
     t = hobo.Tensor.from_terms(terms)
-    g = run_gpu(env, t, 4096, 1000, 5.0, 0.01, seed=42, prec=1, algo=BLOCKS, nw=16)[0]
+    g = run_gpu(env, t, 4096, 1000, 5.0, 0.01, seed=42, prec=prec, algo=BLOCKS, nw=16)[0]
+    drift = abs(g["trace"][-1] - g["best_e"].min())
+    print(f"tracked-vs-FP64 drift of the best replica: {drift:.3e} (E = {g['best_e'].min():.6f})")
+    assert drift <= 1e-5 * abs(g["best_e"].min())
     want = oracle.energy(c, g["best_bits"])
     rows = np.random.default_rng(1).choice(4096, size=64, replace=False)
     floor = float(np.median(oracle.active_scale(c, g["best_bits"][:, rows])))
@@ -280,3 +286,86 @@ def test_real3_full_size_blocked_anneal(env):
     assert (np.diff(g["trace"]) <= 0).all()
     o = oracle.anneal(c, 16, 1000, 5.0, 0.01, seed=42)
     assert abs(np.median(g["best_e"][:16]) - np.median(o["best_e"])) < 0.02 * abs(np.median(o["best_e"]))
+
+
+def _split_int_instance(seed, n, big_bits):
+    """Order-3 integer instance whose coefficients need every part of a
+    split: most are uniform in [-2^13, 2^13] (up to 14 significant bits: the
+    BF16 hi part alone holds 8), and with big_bits > 17 a dozen odd values of
+    magnitude in [2^16, 2^big_bits) need a third BF16 part (hi + lo hold 17
+    bits with their signs).  sum |w| stays below 2^24, so FP32 sums stay
+    exact."""
+    rng = np.random.default_rng(seed)
+    subs, co = [], []
+    for r in (1, 2, 3):
+        s = W.lex_subsets(n, r)
+        v = rng.integers(-(1 << 13), (1 << 13) + 1, size=len(s))
+        subs.append(s)
+        co.append(v)
+    if big_bits > 16:
+        k = 40 if big_bits <= 17 else 12
+        pos = rng.choice(len(co[2]), size=k, replace=False)
+        mag = rng.integers(1 << 15, 1 << (big_bits - 1), size=k) * 2 + 1
+        co[2][pos] = mag * rng.choice([-1, 1], size=k)
+    total = sum(int(np.abs(c).sum()) for c in co)
+    assert total < (1 << 24), total
+    return W.subsets_to_terms(n, subs, co, True)
+
+
+@pytest.mark.parametrize("prec,big,algo", [(1, 17, SLABS), (1, 17, BLOCKS), (2, 19, SLABS), (2, 19, BLOCKS),
+                                           (5, 19, SLABS), (5, 19, BLOCKS)])
+def test_split_integer_trajectory(env, prec, big, algo):
+    """Trajectory identity on integer coefficients that the first BF16 part
+    cannot hold (and, for BF16X3, that the first two cannot): a dropped or
+    wrong lo / mid pass in the field or coupling tiles changes the flip
+    changes and therefore the chain."""
+    hobo, _ = env
+    terms = _split_int_instance(50 + prec, 24, big)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    g = run_gpu(env, t, 48, 20, 4e4, 2e2, seed=61, prec=prec, algo=algo)[0]
+    o = oracle.anneal(c, 48, 20, 4e4, 2e2, seed=61)
+    assert o["accepts"] > 48 * 10  # the chains move
+    assert_same(g, o)
+
+
+# bound on |dE_gpu - dE| / A (A = sum of |w| over the visited bit's active
+# monomials): FP32 summation of a few hundred partial sums (n 2^-24 with n up
+# to ~1600 sequential roundings, 1e-4), plus the split's representation error
+# per coefficient (BF16X2: 2^-16; FP16X2: 2^-22; BF16X3 and FP32: exact for
+# FP32 coefficients)
+DECISION_EPS = {0: 1e-4, 1: 1e-4 + 2.0 ** -16, 2: 1e-4, 5: 1e-4 + 2.0 ** -22}
+
+
+@pytest.mark.parametrize("prec,algo", [(0, BLOCKS), (1, BLOCKS), (2, BLOCKS), (5, BLOCKS), (0, SLABS), (5, SLABS)])
+def test_real_trajectory_decisions(env, prec, algo):
+    """Element-wise annealer parity on real coefficients (N=128 order 3, 64
+    replicas, 20 sweeps of a 2.0 -> 0.2 schedule).  Each sweep starts both
+    sides from the GPU's states; the oracle also returns, per replica and
+    sweep, the smallest decision margin |dE beta + ln u| / (beta A).  Where
+    that margin exceeds the precision's error bound on dE / A, no decision of
+    the sweep can differ, so the GPU's states must equal the oracle's; where a
+    replica's states differ, the sweep must hold a decision within the bound
+    (a near-tie)."""
+    hobo, torch = env
+    n, B, S = 128, 64, 20
+    terms = W.cfg_real3(seed=3, n=n)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    x = W.pack_bits(W.random_states(n, B, seed=44))
+    eps = DECISION_EPS[prec]
+    exact = ties = moved = 0
+    for s in range(S):
+        o = oracle.anneal(c, B, 1, 2.0, 0.2, seed=9, init_bits=x, first_sweep=s, schedule_sweeps=S, margins=True)
+        g = run_gpu(env, t, B, 1, 2.0, 0.2, seed=9, prec=prec, algo=algo, init_bits=[x], first=s, total=S)[0]
+        same = (g["final_bits"] == o["final_bits"]).all(axis=0)
+        m = o["margin"][:, 0]
+        far = m > eps
+        assert same[far].all(), (s, np.nonzero(far & ~same)[0])
+        assert (m[~same] <= eps).all()
+        exact += int(far.sum())
+        ties += int((~same).sum())
+        moved += int((g["final_bits"] != x).any(axis=0).sum())
+        x = g["final_bits"]
+    print(f"replica-sweeps checked exactly: {exact} of {B * S}; near-tie divergences: {ties}; moved: {moved}")
+    assert exact >= 0.6 * B * S and moved >= 0.5 * B * S

@@ -1,8 +1,10 @@
 """GPU parity: the HIP kernels against the CPU oracle on the same seeded
 inputs.  Integer instances must match bit for bit; real instances within
 |E - E*| <= tol * max(|E*|, s(x)), s(x) = sqrt(sum of squared active terms),
-with tol = 1e-5 (FP32, BF16X3) and 2e-5 (BF16X2, whose coefficients carry a
-2^-18 relative split error)."""
+with tol = 1e-5 (FP32, BF16X3, FP16X2) and 2e-5 for BF16X2: its coefficients
+carry a split error of up to 2^-16 of each value (about 2^-18 on average),
+and its largest measured error on the N=128 order-3 workload is 1.2-1.4e-5,
+so BF16X2 does not meet 1e-5 and is not the benchmark's headline precision."""
 import numpy as np
 import pytest
 
@@ -11,7 +13,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-5, 1: 2e-5, 2: 1e-5}
+TOL = {0: 1e-5, 1: 2e-5, 2: 1e-5, 5: 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -45,8 +47,8 @@ def gpu_fields(env, t, bits_np, prec, want_e=True):
     return de.cpu().numpy(), (e.cpu().numpy() if want_e else None)
 
 
-INT_PRECS = [0, 1, 2, 3]
-REAL_PRECS = [0, 1, 2]
+INT_PRECS = [0, 1, 2, 3, 5]
+REAL_PRECS = [0, 1, 2, 5]
 
 
 def _int_instance(seed, n, k, lo=-6, hi=6, dens=0.8):
@@ -175,7 +177,7 @@ def test_degenerate_instances(env):
     c = oracle.canonicalize(terms)
     t = hobo.Tensor.from_terms(terms)
     bits = W.pack_bits(W.random_states(9, 50, seed=2))
-    for prec in (0, 1, 3):
+    for prec in (0, 1, 3, 5):
         np.testing.assert_array_equal(gpu_energy(env, t, bits, prec), oracle.energy(c, bits))
         de, e = gpu_fields(env, t, bits, prec)
         np.testing.assert_array_equal(de, oracle.fields(c, bits)[1])
@@ -243,3 +245,66 @@ def test_real3_full_batch_sampled(env, prec):
     # rows' median active scale as the floor
     floor = float(np.median(scale))
     assert np.max(np.abs(e_gpu - e_f) / np.maximum(np.abs(e_gpu), floor)) <= 2 * TOL[prec]
+
+
+def _split_ints(seed, n, lo_bits, big_bits, count):
+    """Order-3 integer instance: coefficients uniform with up to lo_bits
+    significant bits, plus `count` odd ones with big_bits (sum |w| < 2^24)."""
+    rng = np.random.default_rng(seed)
+    subs, co = [], []
+    for r in (1, 2, 3):
+        s = W.lex_subsets(n, r)
+        subs.append(s)
+        co.append(rng.integers(-(1 << (lo_bits - 1)), (1 << (lo_bits - 1)) + 1, size=len(s)))
+    if count:
+        pos = rng.choice(len(co[2]), size=count, replace=False)
+        co[2][pos] = (rng.integers(1 << (big_bits - 2), 1 << (big_bits - 1), size=count) * 2 + 1) * \
+            rng.choice([-1, 1], size=count)
+    assert sum(int(np.abs(c).sum()) for c in co) < (1 << 24)
+    return W.subsets_to_terms(n, subs, co, True)
+
+
+@pytest.mark.parametrize("prec,lo_bits,big_bits,count", [(1, 15, 0, 0), (2, 12, 19, 12), (5, 12, 21, 6)])
+def test_split_integers_exact(env, prec, lo_bits, big_bits, count):
+    """Integer coefficients that need every part of the split (BF16X2: 15
+    significant bits, more than the 8 of the hi part; BF16X3: odd 19-bit
+    values, more than the 17 that hi + lo hold with their signs; FP16X2: odd
+    21-bit values with its power-of-two scale): energies and flip changes
+    bit-exact; BF16X2 refuses the instances its two parts cannot hold."""
+    hobo, _ = env
+    terms = _split_ints(70 + prec, 20, lo_bits, big_bits, count)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(20, 300, seed=9))
+    np.testing.assert_array_equal(gpu_energy(env, t, bits, prec), oracle.energy(c, bits))
+    de, e = gpu_fields(env, t, bits, prec)
+    np.testing.assert_array_equal(de, oracle.fields(c, bits)[1])
+    np.testing.assert_array_equal(e, oracle.energy(c, bits))
+    if count:
+        with pytest.raises(hobo.HoboError) as ei:
+            gpu_energy(env, t, bits, 1)
+        assert ei.value.code == hobo.ERR_RANGE
+
+
+def test_fp16x2_accuracy_margin(env):
+    """On the N=128 order-3 workload the FP16 pair (22 significant bits per
+    coefficient) is as accurate as plain FP32: its error, relative to the
+    |E*| / s(x) floor, stays within 1.5x of FP32's (both are set by the FP32
+    sums) and at most 5e-6, where BF16X2's 16-bit coefficients reach about
+    1e-5."""
+    hobo, _ = env
+    terms = W.cfg_real3(seed=4)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(128, 256, seed=13))
+    want = oracle.energy(c, bits)
+    scale = oracle.active_scale(c, bits)
+    errs = {}
+    for prec in (5, 1, 0):
+        e = gpu_energy(env, t, bits, prec)
+        de, _ = gpu_fields(env, t, bits, prec, want_e=False)
+        _, de_ref = oracle.fields(c, bits)
+        fscale = oracle.field_scale(c, bits)
+        errs[prec] = max(_rel_err(e, want, scale).max(), _rel_err(de.astype(np.float64), de_ref, fscale).max())
+    print(f"max error / C13 floor: FP16X2 {errs[5]:.2e}, BF16X2 {errs[1]:.2e}, FP32 {errs[0]:.2e}")
+    assert errs[5] <= 5e-6 and errs[5] <= 1.5 * errs[0] and errs[5] < errs[1] / 2
