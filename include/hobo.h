@@ -171,6 +171,23 @@ hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_
 hobo_status hobo_energy(const hobo_tensor* t, const uint64_t* x_bits, int64_t B,
                         int32_t precision, void* e_out, void* stream);
 
+/* hobo_energy without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and kernels as hobo_energy.
+ * Its workspace is a per-GPU scratch array of 32 MiB inside the library,
+ * held until the process ends; the batch is refused (HOBO_ERR_INVALID_ARG)
+ * when it needs more (tiled precisions: 8 B x max(16-column tiles, column
+ * groups) x B, e.g. B <= 524288 at N = 128; FP64: 8 B x ceil(monomials /
+ * 4096) x B plus the replica masks).  The tensor's layout for the precision
+ * must already be on the device (hobo_tensor_prepare with fn 1 and the
+ * precision's bit), else HOBO_ERR_INVALID_ARG.  Every call on a GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  No hipMemsetAsync
+ * is issued, so the call may be captured into a graph (with
+ * hobo_timing_enable off). */
+hobo_status hobo_energy_noalloc(const hobo_tensor* t, const uint64_t* x_bits, int64_t B, int32_t precision,
+                                void* e_out, void* stream);
+
 /* Batched single-flip energy changes dE_{b,i} = f(x_b xor e_i) - f(x_b)
  * = (1 - 2 x_{b,i}) g_{b,i}, with the local field
  * g_{b,i} = sum_{S containing i} w_S prod_{j in S, j != i} x_{b,j},

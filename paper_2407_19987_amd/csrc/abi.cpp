@@ -459,6 +459,57 @@ hobo_status hobo_energy(const hobo_tensor* tc, const uint64_t* x_bits, int64_t B
   return ok();
 }
 
+hobo_status hobo_energy_noalloc(const hobo_tensor* tc, const uint64_t* x_bits, int64_t B, int32_t precision,
+                                void* e_out, void* stream) {
+  g_err.clear();
+  if (hobo_status s = check_bits_args(tc, x_bits, B, precision)) return s;
+  if (!e_out) return fail(HOBO_ERR_INVALID_ARG, "e_out is NULL");
+  if (hobo_status s = need_device()) return s;
+  hobo_tensor* t = const_cast<hobo_tensor*>(tc);
+  std::string err;
+  void* scratch = nullptr;
+  if (int s = hobo::noalloc_scratch(&scratch, &err)) return fail(s, err);
+  if (t->t.n_mono() == 0) {
+    if (int s = hobo::launch_zero_u64(e_out, B, stream, &err)) return fail(s, err);
+    return ok();
+  }
+  const size_t cap = hobo::kNoallocScratchBytes;
+  if (precision == HOBO_PREC_FP64) {
+    hobo::TermsDev* td = nullptr;
+    {
+      std::lock_guard<std::mutex> lock(t->t.mu);
+      td = t->t.terms.get();
+    }
+    if (!td)
+      return fail(HOBO_ERR_INVALID_ARG, "FP64 term list not on the device: call hobo_tensor_prepare(t, 1, 1 << FP64) first");
+    const size_t need = hobo::term_workspace_bytes(&t->t, B);
+    if (need > cap)
+      return fail(HOBO_ERR_INVALID_ARG, "batch needs " + std::to_string(need) + " bytes of workspace; the no-allocation "
+                  "scratch holds " + std::to_string(cap));
+    hobo::TermArgs a{td, &t->t, x_bits, B, e_out, scratch, stream};
+    if (int s = hobo::launch_term_energy(a, &err)) return fail(s, err);
+    return ok();
+  }
+  hobo::Packed* pk = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(t->t.mu);
+    auto it = t->t.packed.find(hobo::M_ENERGY * 16 + precision);
+    if (it != t->t.packed.end()) pk = it->second.get();
+  }
+  if (!pk)
+    return fail(HOBO_ERR_INVALID_ARG, "energy layout of this precision not on the device: call "
+                "hobo_tensor_prepare(t, 1, 1 << precision) first");
+  int rt, ct;
+  eval_shape(t->t, precision, B, &rt, &ct, hobo::TK_ENERGY);
+  const size_t need = hobo::eval_workspace_bytes(&t->t, hobo::M_ENERGY, B, ct);
+  if (need > cap)
+    return fail(HOBO_ERR_INVALID_ARG, "batch needs " + std::to_string(need) + " bytes of workspace; the no-allocation "
+                "scratch holds " + std::to_string(cap));
+  hobo::EvalArgs a{pk, &t->t, x_bits, B, nullptr, e_out, need ? scratch : nullptr, rt, ct, stream};
+  if (int s = hobo::launch_eval(a, &err)) return fail(s, err);
+  return ok();
+}
+
 hobo_status hobo_local_fields(const hobo_tensor* tc, const uint64_t* x_bits, int64_t B, int32_t precision,
                               void* de_out, void* e_out, void* stream) {
   g_err.clear();

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -116,6 +117,46 @@ int launch_eval(const EvalArgs& a, std::string* err) {
     s = hip_fail(hipGetLastError(), err, "reduce kernel launch");
   }
   return s;
+}
+
+// ============================================================ no-allocation scratch
+// Workspace of hobo_energy_noalloc: one array per GPU, held until the
+// process ends, shared by every call on that GPU (calls that overlap on one
+// GPU race on it).  In host code the symbol's name is not a device address;
+// noalloc_scratch resolves the address once per device with
+// hipGetSymbolAddress and every launch takes that pointer.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+int noalloc_scratch(void** out, std::string* err) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDev] = {};
+  int dev = 0;
+  if (int s = hip_fail(hipGetDevice(&dev), err, "hipGetDevice")) return s;
+  if (dev < 0 || dev >= kMaxDev) {
+    *err = "device index beyond the no-allocation scratch table";
+    return HOBO_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (int s = hip_fail(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), err, "hipGetSymbolAddress(scratch)")) return s;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return HOBO_OK;
+}
+
+__global__ void fill_zero_u64(unsigned long long* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+int launch_zero_u64(void* p, long long n, void* stream, std::string* err) {
+  if (n <= 0) return HOBO_OK;
+  hipLaunchKernelGGL(fill_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     static_cast<unsigned long long*>(p), n);
+  return hip_fail(hipGetLastError(), err, "zero fill launch");
 }
 
 size_t term_workspace_bytes(const Tensor* t, int64_t B) {

@@ -235,6 +235,13 @@ struct EvalArgs {
 int launch_eval(const EvalArgs& a, std::string* err);
 size_t eval_workspace_bytes(const Tensor* t, int mode, int64_t B, int ct);
 
+// no-allocation entry point: size of the per-GPU scratch array, its device
+// address on the current device (resolved once per device), and a zero fill
+// kernel (no hipMemsetAsync, so that callers may capture the call)
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+int noalloc_scratch(void** out, std::string* err);
+int launch_zero_u64(void* p, long long n, void* stream, std::string* err);
+
 struct TermArgs {
   const TermsDev* td;
   const Tensor* t;

@@ -35,7 +35,7 @@ EXPORTS = [
     "hobo_tensor_export_dense", "hobo_tensor_prepare", "hobo_energy", "hobo_local_fields",
     "hobo_anneal_batch", "hobo_timing_enable", "hobo_timing_read", "hobo_last_error", "hobo_version",
     "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features", "hobo_autotune",
-    "hobo_tensor_layout_info",
+    "hobo_tensor_layout_info", "hobo_energy_noalloc",
 ]
 
 
@@ -84,6 +84,7 @@ def _load():
     lib.hobo_tensor_prepare.argtypes = [P, u32, u32]
     lib.hobo_tensor_layout_info.argtypes = [P, i32, i32, ctypes.POINTER(LayoutInfo)]
     lib.hobo_energy.argtypes = [P, P, i64, i32, P, P]
+    lib.hobo_energy_noalloc.argtypes = [P, P, i64, i32, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
     lib.hobo_mlp_forward.argtypes = [P, P, i64, P, P]
@@ -218,6 +219,16 @@ def energy(t: Tensor, x_bits, B: int, precision: int, e_out, stream=None):
     if e_out.numel() < B or e_out.element_size() != 8:
         raise ValueError("e_out must hold B 8-byte values")
     _check(lib.hobo_energy(t.handle, _dev_ptr(x_bits), int(B), int(precision), _dev_ptr(e_out), _stream(stream)))
+
+
+def energy_noalloc(t: Tensor, x_bits, B: int, precision: int, e_out, stream=None):
+    """hobo_energy_noalloc: as energy(), with the library's per-GPU scratch
+    instead of any allocation (the layout must be prepared first)."""
+    _check_bits(t, x_bits, B)
+    if e_out.numel() < B or e_out.element_size() != 8:
+        raise ValueError("e_out must hold B 8-byte values")
+    _check(lib.hobo_energy_noalloc(t.handle, _dev_ptr(x_bits), int(B), int(precision), _dev_ptr(e_out),
+                                   _stream(stream)))
 
 
 def local_fields(t: Tensor, x_bits, B: int, precision: int, de_out, e_out=None, stream=None):
