@@ -278,6 +278,24 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances,
                               uint64_t* x_inout, uint64_t* best_x_out, void* best_e_out,
                               double* trace_out, int32_t launch_mode, void* stream);
 
+/* ------------------------------------------------------------- results */
+/* The result list of a sampling run (the paper's Sec. V result blocks: each
+ * distinct state found among the `shots` samples, with its energy and number
+ * of occurrences, best first).  Host-side, no device work.
+ *  n_vars     : N, 1..256
+ *  B          : samples (>= 0)
+ *  x_bits     : host uint64 [W][B] (the layout of hobo_anneal_batch's outputs)
+ *  energies   : host int64[B] (is_integer) or double[B] (no NaN), e.g. the
+ *               exact energies hobo_anneal_batch returns for best_x
+ *  n_unique   : receives U, the number of distinct states
+ *  rep_out    : host int64[B]; rep_out[u] = the first sample holding state u
+ *  count_out  : host int64[B]; count_out[u] = the samples holding state u
+ * States are ordered by energy (ascending), then by the bit sequence
+ * x_0, x_1, ... (lexicographic; the paper leaves the order of equal
+ * energies open); samples with equal bits and equal energies are one state. */
+hobo_status hobo_aggregate(int32_t n_vars, int64_t B, const uint64_t* x_bits, const void* energies,
+                           int32_t is_integer, int64_t* n_unique, int64_t* rep_out, int64_t* count_out);
+
 /* ------------------------------------------------------------- learned proposal */
 /* The flip-proposal network: a two-layer perceptron 3 -> 256 -> 1 mapping a
  * bit's features [x_i, beta dE_i, beta ||H_i||] to a flip logit,

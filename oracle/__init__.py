@@ -417,3 +417,28 @@ def anneal(canon: Canonical, n_rep: int, sweeps: int, t_start: float, t_end: flo
     if margins:
         out["margin"] = marg[:, :sweeps]
     return out
+
+
+# --------------------------------------------------------------------------
+# result list of a sampling run
+# --------------------------------------------------------------------------
+
+
+def aggregate(n_vars: int, bits: np.ndarray, energies) -> list:
+    """The paper's result list (Sec. V result blocks): every distinct sampled
+    state with its energy and number of occurrences, ordered by energy, then
+    by the bit sequence (x_0, x_1, ...).  bits [W][B]; returns a list of
+    (bit tuple, energy, count, first sample index)."""
+    w = np.asarray(bits, dtype=np.uint64)
+    B = w.shape[1]
+    rows = {}
+    for b in range(B):
+        key = tuple((int(w[i >> 6, b]) >> (i & 63)) & 1 for i in range(n_vars))
+        e = energies[b]
+        if key in rows:
+            if rows[key][0] != e:
+                raise ValueError("one state with two energies")
+            rows[key][1] += 1
+        else:
+            rows[key] = [e, 1, b]
+    return sorted(((k, v[0], v[1], v[2]) for k, v in rows.items()), key=lambda r: (r[1], r[0]))

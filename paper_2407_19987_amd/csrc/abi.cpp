@@ -9,6 +9,7 @@
 #include <iterator>
 #include <list>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -1078,6 +1079,30 @@ hobo_status hobo_proposal_features(const hobo_tensor* tc, const uint64_t* x_bits
                                       t->t.integer ? 1 : 0, beta, rn, feats_out, labels_out, (hipStream_t)stream,
                                       &err))
     return fail(s, err);
+  return ok();
+}
+
+// ------------------------------------------------------------ results
+hobo_status hobo_aggregate(int32_t n_vars, int64_t B, const uint64_t* x_bits, const void* energies,
+                           int32_t is_integer, int64_t* n_unique, int64_t* rep_out, int64_t* count_out) {
+  g_err.clear();
+  if (n_vars < 1 || n_vars > hobo::kMaxVars) return fail(HOBO_ERR_INVALID_ARG, "n_vars out of range");
+  if (B < 0) return fail(HOBO_ERR_INVALID_ARG, "B must be >= 0");
+  if (B > 0 && (!x_bits || !energies || !rep_out || !count_out))
+    return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (!n_unique) return fail(HOBO_ERR_INVALID_ARG, "n_unique is NULL");
+  if (B == 0) {
+    *n_unique = 0;
+    return ok();
+  }
+  std::string err;
+  try {
+    if (int s = hobo::aggregate_states(n_vars, B, x_bits, energies, is_integer ? 1 : 0, n_unique, rep_out, count_out,
+                                       &err))
+      return fail(s, err);
+  } catch (const std::bad_alloc&) {
+    return fail(HOBO_ERR_OOM, "host allocation failed");
+  }
   return ok();
 }
 

@@ -193,6 +193,12 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
                  const int32_t* term_idx, const void* coeff, int coeff_type, Tensor* t,
                  std::string* err);
 
+// results.cpp -- unique states of a batch (host buffers), ordered by energy
+// then by the bit sequence x_0, x_1, ...; per unique state the first replica
+// holding it and its number of replicas
+int aggregate_states(int n_vars, int64_t B, const uint64_t* x_bits, const void* energies, int is_integer,
+                     int64_t* n_unique, int64_t* rep_out, int64_t* count_out, std::string* err);
+
 // pack.cpp -- whether a precision can represent the tensor exactly enough
 // (host-only checks: INT8X4 needs an integer tensor whose digit and energy
 // sums fit; FP32 / BF16 on an integer tensor need sum |w| < 2^24)

@@ -10,6 +10,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch (the device-memory and stream provider) is loaded before the library:
+# the library then binds to the HIP runtime torch already holds, and both see
+# the same devices whatever the import order of the caller
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhobo.so")
@@ -35,7 +39,7 @@ EXPORTS = [
     "hobo_tensor_export_dense", "hobo_tensor_prepare", "hobo_energy", "hobo_local_fields",
     "hobo_anneal_batch", "hobo_timing_enable", "hobo_timing_read", "hobo_last_error", "hobo_version",
     "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features", "hobo_autotune",
-    "hobo_tensor_layout_info", "hobo_energy_noalloc",
+    "hobo_tensor_layout_info", "hobo_energy_noalloc", "hobo_aggregate",
 ]
 
 
@@ -85,6 +89,7 @@ def _load():
     lib.hobo_tensor_layout_info.argtypes = [P, i32, i32, ctypes.POINTER(LayoutInfo)]
     lib.hobo_energy.argtypes = [P, P, i64, i32, P, P]
     lib.hobo_energy_noalloc.argtypes = [P, P, i64, i32, P, P]
+    lib.hobo_aggregate.argtypes = [i32, i64, P, P, i32, P, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
     lib.hobo_mlp_forward.argtypes = [P, P, i64, P, P]
@@ -375,3 +380,22 @@ def bits_to_device(bits_np: np.ndarray):
 
 def bits_to_host(bits_dev) -> np.ndarray:
     return bits_dev.cpu().numpy().view(np.uint64)
+
+
+def aggregate(n_vars: int, bits_host: np.ndarray, energies_host: np.ndarray):
+    """hobo_aggregate on host arrays: bits [W][B] uint64, energies [B] int64 or
+    float64.  Returns (representative sample index [U], count [U]), best first."""
+    bits = np.ascontiguousarray(bits_host, dtype=np.uint64)
+    e = np.ascontiguousarray(energies_host)
+    integer = e.dtype.kind in "iu"
+    e = np.ascontiguousarray(e, dtype=np.int64 if integer else np.float64)
+    B = e.shape[0]
+    if bits.shape != ((n_vars + 63) // 64, B):
+        raise ValueError("bits must be [W][B]")
+    rep = np.zeros(max(B, 1), dtype=np.int64)
+    cnt = np.zeros(max(B, 1), dtype=np.int64)
+    nu = np.zeros(1, dtype=np.int64)
+    _check(lib.hobo_aggregate(int(n_vars), int(B), _np_ptr(bits), _np_ptr(e), 1 if integer else 0, _np_ptr(nu),
+                              _np_ptr(rep), _np_ptr(cnt)))
+    u = int(nu[0])
+    return rep[:u], cnt[:u]

@@ -282,62 +282,72 @@ def cfg_mixed_instance(master_seed: int, index: int, n_lo: int = 24, n_hi: int =
 # --------------------------------------------------------------------------
 
 
+def pseudo_boolean_terms(n_vars: int, values: np.ndarray, name: str = "") -> TermList:
+    """The unique multilinear polynomial that takes values[m] at the state
+    whose bit i is bit i of m (all 2^n states, integers): its coefficients
+    are the Moebius transform of the values over the subset lattice,
+    w_S = sum over T subset of S of (-1)^(|S|-|T|) f(T); the empty set's
+    coefficient is the offset."""
+    w = np.array(values, dtype=np.int64).copy()
+    if w.shape != (1 << n_vars,):
+        raise ValueError("one value per state")
+    for i in range(n_vars):
+        bit = 1 << i
+        idx = np.nonzero(np.arange(1 << n_vars) & bit)[0]
+        w[idx] -= w[idx ^ bit]
+    masks = np.nonzero(w)[0]
+    subsets = {}
+    for m in masks:
+        vs = [i for i in range(n_vars) if (int(m) >> i) & 1]
+        subsets.setdefault(len(vs), []).append((vs, int(w[m])))
+    subs, co = [], []
+    for r in sorted(subsets):
+        rows = [v for v, _ in subsets[r]]
+        subs.append(np.zeros((len(rows), 0), dtype=np.int64) if r == 0 else np.array(rows, dtype=np.int64))
+        co.append(np.array([c for _, c in subsets[r]], dtype=np.int64))
+    return subsets_to_terms(n_vars, subs, co, True, name=name)
+
+
 def paper_seating(grid: int = 5, run: int = 3, penalty: int = 10) -> TermList:
-    """Sec. V.A: reward every occupied seat (-1 each), penalise (x10) every
-    `run` consecutive occupied seats in a row or a column.  Variable of seat
-    (i, j) is i*grid + j."""
-    q = [[RawPoly.var(i * grid + j) for j in range(grid)] for i in range(grid)]
-    h1 = RawPoly()
-    for i in range(grid):
-        for j in range(grid):
-            h1 = h1 - q[i][j]
-    h2 = RawPoly()
-    for i in range(grid):
-        for j in range(grid - run + 1):
-            prod = RawPoly.const(1)
-            for d in range(run):
-                prod = prod * q[i][j + d]
-            h2 = h2 + prod
-    for j in range(grid):
-        for i in range(grid - run + 1):
-            prod = RawPoly.const(1)
-            for d in range(run):
-                prod = prod * q[i + d][j]
-            h2 = h2 + prod
-    t = poly_to_terms(grid * grid, h1 + penalty * h2, True, "paper_seating")
+    """Sec. V.A: `grid` x `grid` seats; one point for every occupied seat and
+    a penalty for every `run` consecutive occupied seats along a row or a
+    column: cost = -(occupied seats) + penalty x (fully occupied windows).
+    Variable of seat (i, j) is i*grid + j."""
+    windows = [[i * grid + j + d for d in range(run)] for i in range(grid) for j in range(grid - run + 1)]
+    windows += [[(i + d) * grid + j for d in range(run)] for j in range(grid) for i in range(grid - run + 1)]
+    singles = np.arange(grid * grid, dtype=np.int64).reshape(-1, 1)
+    t = subsets_to_terms(grid * grid, [singles, np.array(windows, dtype=np.int64)],
+                         [-np.ones(grid * grid, dtype=np.int64), np.full(len(windows), penalty, dtype=np.int64)],
+                         True, name="paper_seating")
     t.meta.update(order=run, family="paper")
     return t
 
 
 def paper_pythagorean(bits: int = 4, penalty: int = 10) -> TermList:
-    """Sec. V.B: integers x, y, z with `bits`-bit binary codes (variable of bit
-    a of integer p is p*bits + a); cost (x^2 + y^2 - z^2)^2 plus `penalty`
-    times, for each integer, the product of (1 - bit) over its bits (an
-    all-zero integer is penalised)."""
-    v = [[RawPoly.var(p * bits + a) for a in range(bits)] for p in range(3)]
-    xs = [sum((v[p][a] * (1 << a) for a in range(bits)), RawPoly()) for p in range(3)]
-    h1 = (xs[0] * xs[0] + xs[1] * xs[1] - xs[2] * xs[2]) ** 2
-    h2 = RawPoly()
-    for p in range(3):
-        prod = RawPoly.const(1)
-        for a in range(bits):
-            prod = prod * (1 - v[p][a])
-        h2 = h2 + prod
-    t = poly_to_terms(3 * bits, h1 + penalty * h2, True, "paper_pythagorean")
+    """Sec. V.B: integers x, y, z, each a `bits`-bit binary code (Sec. IV.B:
+    bit a of integer p is variable p*bits + a, weight 2^a); the cost is
+    (x^2 + y^2 - z^2)^2 plus `penalty` for each integer that is 0.  The terms
+    are the multilinear expansion of that cost over all 2^(3 bits) states."""
+    n = 3 * bits
+    m = np.arange(1 << n, dtype=np.int64)
+    ints = [(m >> (p * bits)) & ((1 << bits) - 1) for p in range(3)]
+    f = (ints[0] ** 2 + ints[1] ** 2 - ints[2] ** 2) ** 2 + penalty * sum((v == 0).astype(np.int64) for v in ints)
+    t = pseudo_boolean_terms(n, f, "paper_pythagorean")
     t.meta.update(order=4, family="paper", bits=bits)
     return t
 
 
 def paper_tsp_intenc(penalty: int = 10, target: int = 6) -> TermList:
-    """Sec. V.C: three 2-bit integers (most significant bit first in the
-    listing: x = 2*q_{p,0} + q_{p,1}); cost penalty * (xB*xC*xD - target)^2.
-    The listing declares a fourth, unused integer; only the six used bits are
-    variables here (variable 2p + a for q_{p,a}), which is the paper's
-    dimension reduction of Sec. IV.D."""
-    q = [[RawPoly.var(2 * p + a) for a in range(2)] for p in range(3)]
-    xs = [2 * q[p][0] + q[p][1] for p in range(3)]
-    h = penalty * (xs[0] * xs[1] * xs[2] - target) ** 2
-    t = poly_to_terms(6, h, True, "paper_tsp")
+    """Sec. V.C: three 2-bit integers x_p = 2 q_{p,0} + q_{p,1} (the first
+    bit is the more significant one); cost penalty * (x_B x_C x_D - target)^2.
+    The formulation declares a fourth, unused integer; only the six used bits
+    are variables here (variable 2p + a for q_{p,a}), which is the paper's
+    dimension reduction of Sec. IV.D.  The terms are the multilinear expansion
+    of the cost over all 64 states."""
+    m = np.arange(64, dtype=np.int64)
+    xs = [2 * ((m >> (2 * p)) & 1) + ((m >> (2 * p + 1)) & 1) for p in range(3)]
+    f = penalty * (xs[0] * xs[1] * xs[2] - target) ** 2
+    t = pseudo_boolean_terms(6, f, "paper_tsp")
     t.meta.update(order=6, family="paper")
     return t
 
