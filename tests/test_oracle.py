@@ -452,3 +452,50 @@ def test_anneal_margins_by_hand():
                     x = y
             assert res["margin"][b, s] == pytest.approx(mm, rel=1e-9, abs=1e-13)
         assert W.unpack_bits(res["final_bits"], n)[b].tolist() == x
+
+
+# ---------------------------------------------------------- TT decomposition
+
+
+def test_tt_svd_of_the_tsp_tensor(golden):
+    """Sec. VI.F: the exact TT decomposition of the (6,)^6 TSP tensor has the
+    printed core shapes (ranks 2, 3, 4, 4, 2), reproduces the tensor, gives
+    every state's energy through the cores, and its contraction with the
+    six x vectors has the printed einsum-path counts."""
+    import oracle.tt as TT
+
+    g = golden["tsp_intenc"]
+    c = _canon(W.paper_tsp_intenc())
+    h = oracle.paper_tensor(c).astype(np.float64)
+    cores, ranks = TT.tt_svd(h)
+    assert ranks == [2, 3, 4, 4, 2]
+    shapes = [list(cores[0].shape[1:])] + [list(x.shape) for x in cores[1:-1]] + [list(cores[-1].shape[:2])]
+    assert shapes == g["tt_core_shapes"]
+    assert np.abs(TT.tt_full(cores) - h).max() < 1e-9
+    x = W.all_states(6)
+    np.testing.assert_allclose(TT.tt_energies(cores, x), oracle.energy(c, W.pack_bits(x)), rtol=0, atol=1e-9)
+    v = np.ones(6)
+    ops = [v] * 6 + [cores[0][0]] + [x for x in cores[1:-1]] + [cores[-1][:, :, 0]]
+    _, text = np.einsum_path("i,j,k,l,m,n,iA,AjB,BkC,ClD,DmE,En->", *ops, optimize="greedy")
+    t = g["einsum_tt"]
+    assert f"{t['naive_flops']:.3e}" in text
+    assert f"{t['optimized_flops']:.3e}" in text
+    assert f"{t['largest_intermediate']:.3e}" in text
+
+
+@pytest.mark.parametrize("seed,n,k,integer", [(1, 7, 3, True), (2, 5, 4, False), (3, 9, 2, True), (4, 4, 5, False)])
+def test_tt_energies_equal_the_definition(seed, n, k, integer):
+    """Random instances: the TT form's energies equal the term sums on every
+    state (brute force), and each rank is the rank of its unfolding."""
+    import oracle.tt as TT
+
+    terms = _rand_int_instance(seed, n, k) if integer else _rand_real_instance(seed, n, k)
+    c = _canon(terms)
+    h = oracle.paper_tensor(c).astype(np.float64)
+    cores, ranks = TT.tt_svd(h)
+    d = h.ndim
+    assert ranks == [int(np.linalg.matrix_rank(h.reshape(n ** j, -1))) for j in range(1, d)]
+    x = W.all_states(n)
+    want = oracle.energy(c, W.pack_bits(x))
+    scale = np.abs(np.asarray(c.weights, dtype=np.float64)).sum()
+    assert np.abs(TT.tt_energies(cores, x) - want).max() <= 1e-12 * scale * n ** 2
