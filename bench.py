@@ -217,6 +217,7 @@ def main():
     if not args.no_eval_sweep:
         eval_info = eval_rates(hobo, W, torch, dev, t, B)
         eval_info.update(int8_rates(hobo, W, torch, dev))
+        eval_info.update(tt_rates(hobo, W, torch, dev))
 
     multi = None
     if args.mixed_instances > 0:
@@ -344,6 +345,33 @@ def int8_rates(hobo, W, torch, dev, bb=8192):
         useful = (2 * sum(nnz) if fn == "energy" else 2 * sum(r * c for r, c in enumerate(nnz))) * rate / 1e12
         out[f"intenc4_{fn}_int8x4_B{bb}"] = dict(us=us, evals_per_s=rate, issued_tops=issued, dense_tops=dense,
                                                  useful_tops=useful, frac_of_peak=issued / PEAK_TFLOPS["int8x4"])
+    return out
+
+
+def tt_rates(hobo, W, torch, dev, bb=65536):
+    """Energies through the tensor-train cores (Sec. VI.F) of the integer-
+    encoded TSP instance (N=6, order 6, ranks 2-4) and of a dense order-3
+    N=16 instance: evaluations per second and the FP64 rate of the core
+    contraction (2 N sum_k r_{k-1} r_k flops per state) against the FP64
+    vector peak (78.6 TFLOP/s)."""
+    out = {}
+    for name, terms in (("tsp_n6_k6", W.paper_tsp_intenc()), ("real3_n16", W.cfg_real3(seed=0, n=16))):
+        tt = hobo.TensorTrain(hobo.Tensor.from_terms(terms))
+        xe = hobo.bits_to_device(W.pack_bits(W.random_states(tt.n_vars, bb, seed=2200)))
+        ee = torch.empty(bb, dtype=torch.float64, device=dev)
+        tt.energy(xe, bb, ee)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            tt.energy(xe, bb, ee)
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) / 10 * 1e3
+        flops = 2 * tt.n_vars * sum(tt.ranks[k] * tt.ranks[k + 1] for k in range(tt.order))
+        tfl = flops * bb / (us * 1e-6) / 1e12
+        out[f"tt_{name}_B{bb}"] = dict(us=us, evals_per_s=bb / (us * 1e-6), ranks=tt.ranks, fp64_tflops=tfl,
+                                       frac_of_fp64_vector_peak=tfl / 78.6)
     return out
 
 

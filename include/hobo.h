@@ -278,6 +278,33 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances,
                               uint64_t* x_inout, uint64_t* best_x_out, void* best_e_out,
                               double* trace_out, int32_t launch_mode, void* stream);
 
+/* ------------------------------------------------------------- tensor train */
+/* The tensor-train (TT) form of the HOBO tensor (Sec. VI.E-F): the dense
+ * order-k tensor in the paper's layout, H[i_1..i_k] (a monomial of size r < k
+ * repeats its smallest variable, Sec. III.C), decomposed without
+ * approximation into cores G_j of shape (r_{j-1}, N, r_j), r_0 = r_k = 1, by
+ * the paper's sequence of SVDs (reshape, SVD, keep the left factor, carry
+ * Sigma V* on); singular values at or below sigma_max * max(rows, cols) *
+ * 2^-52 are dropped (the numerical rank).  Energies through the cores,
+ * E(x) = prod_j (sum_i x_i G_j[:, i, :]), cost O(k N r^2) per state instead
+ * of the dense contraction's O(N^k). */
+typedef struct hobo_tt hobo_tt;
+
+/* Decompose t (host work, N^k <= 2^24 entries, every rank <= 32, else
+ * HOBO_ERR_UNSUPPORTED; no device needed).  The cores are copied to the
+ * current device on the first hobo_tt_energy (which then blocks the host).
+ * The handle is the caller's until hobo_tt_free; t may be freed after. */
+hobo_status hobo_tt_build(const hobo_tensor* t, hobo_tt** out);
+hobo_status hobo_tt_free(hobo_tt* tt);
+/* order k, N, ranks [k + 1] (r_0 .. r_k) and the number of core entries;
+ * each pointer may be NULL. */
+hobo_status hobo_tt_info(const hobo_tt* tt, int32_t* order, int32_t* n_vars, int32_t* ranks, int64_t* n_params);
+/* The cores concatenated, G_j row-major [r_{j-1}][N][r_j], host double[n_params]. */
+hobo_status hobo_tt_cores(const hobo_tt* tt, double* host_out, int64_t capacity);
+/* Energies of B states through the cores (FP64):
+ *  x_bits : device uint64 [W][B];  e_out : device double[B] (offset excluded). */
+hobo_status hobo_tt_energy(const hobo_tt* tt, const uint64_t* x_bits, int64_t B, double* e_out, void* stream);
+
 /* ------------------------------------------------------------- results */
 /* The result list of a sampling run (the paper's Sec. V result blocks: each
  * distinct state found among the `shots` samples, with its energy and number

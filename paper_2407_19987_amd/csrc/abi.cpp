@@ -1082,6 +1082,65 @@ hobo_status hobo_proposal_features(const hobo_tensor* tc, const uint64_t* x_bits
   return ok();
 }
 
+// ------------------------------------------------------------ tensor train
+struct hobo_tt {
+  std::unique_ptr<hobo::TTDev> tt;
+};
+
+hobo_status hobo_tt_build(const hobo_tensor* t, hobo_tt** out) {
+  g_err.clear();
+  if (!t || !out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (t->t.n_mono() == 0) return fail(HOBO_ERR_INVALID_ARG, "the tensor has no monomials");
+  std::string err;
+  std::unique_ptr<hobo_tt> h(new (std::nothrow) hobo_tt());
+  if (!h) return fail(HOBO_ERR_OOM, "host allocation failed");
+  try {
+    if (int s = hobo::tt_decompose(&t->t, &h->tt, &err)) return fail(s, err);
+  } catch (const std::bad_alloc&) {
+    return fail(HOBO_ERR_OOM, "host allocation failed");
+  }
+  *out = h.release();
+  return ok();
+}
+
+hobo_status hobo_tt_free(hobo_tt* tt) {
+  g_err.clear();
+  delete tt;
+  return ok();
+}
+
+hobo_status hobo_tt_info(const hobo_tt* tt, int32_t* order, int32_t* n_vars, int32_t* ranks, int64_t* n_params) {
+  g_err.clear();
+  if (!tt) return fail(HOBO_ERR_INVALID_ARG, "tt is NULL");
+  const hobo::TTDev& d = *tt->tt;
+  if (order) *order = d.order;
+  if (n_vars) *n_vars = d.n;
+  if (ranks)
+    for (int k = 0; k <= d.order; ++k) ranks[k] = d.ranks[(size_t)k];
+  if (n_params) *n_params = (int64_t)d.h_cores.size();
+  return ok();
+}
+
+hobo_status hobo_tt_cores(const hobo_tt* tt, double* host_out, int64_t capacity) {
+  g_err.clear();
+  if (!tt || !host_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  const auto& c = tt->tt->h_cores;
+  if (capacity < (int64_t)c.size()) return fail(HOBO_ERR_INVALID_ARG, "capacity below the number of core entries");
+  std::memcpy(host_out, c.data(), c.size() * sizeof(double));
+  return ok();
+}
+
+hobo_status hobo_tt_energy(const hobo_tt* tt, const uint64_t* x_bits, int64_t B, double* e_out, void* stream) {
+  g_err.clear();
+  if (!tt || !x_bits || !e_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (B < 1 || B > ((int64_t)1 << 40)) return fail(HOBO_ERR_INVALID_ARG, "B out of range");
+  if (hobo_status s = need_device()) return s;
+  std::string err;
+  if (int s = hobo::tt_upload(tt->tt.get(), &err)) return fail(s, err);
+  if (int s = hobo::launch_tt_energy(tt->tt.get(), x_bits, B, e_out, stream, &err)) return fail(s, err);
+  return ok();
+}
+
 // ------------------------------------------------------------ results
 hobo_status hobo_aggregate(int32_t n_vars, int64_t B, const uint64_t* x_bits, const void* energies,
                            int32_t is_integer, int64_t* n_unique, int64_t* rep_out, int64_t* count_out) {

@@ -193,6 +193,24 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
                  const int32_t* term_idx, const void* coeff, int coeff_type, Tensor* t,
                  std::string* err);
 
+// tt.cpp / tt_kernels.hip -- tensor-train form of the HOBO tensor: cores
+// G_k [r_{k-1}][n][r_k] (row-major, concatenated), r_0 = r_d = 1
+constexpr int kTTMaxRank = 32;
+constexpr size_t kTTMaxDense = (size_t)1 << 24;  // entries of the dense tensor it is built from
+struct TTDev {
+  int n = 0, order = 0;
+  std::vector<int> ranks;         // [order + 1]
+  std::vector<int64_t> core_off;  // [order] offsets (in doubles) of the cores
+  std::vector<double> h_cores;
+  double* d_cores = nullptr;       // device copy, made on first use
+  std::mutex mu;
+  ~TTDev();
+};
+int tt_decompose(const Tensor* t, std::unique_ptr<TTDev>* out, std::string* err);
+int tt_upload(TTDev* tt, std::string* err);
+int launch_tt_energy(const TTDev* tt, const uint64_t* bits, int64_t B, double* e_out, void* stream,
+                     std::string* err);
+
 // results.cpp -- unique states of a batch (host buffers), ordered by energy
 // then by the bit sequence x_0, x_1, ...; per unique state the first replica
 // holding it and its number of replicas

@@ -40,6 +40,7 @@ EXPORTS = [
     "hobo_anneal_batch", "hobo_timing_enable", "hobo_timing_read", "hobo_last_error", "hobo_version",
     "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features", "hobo_autotune",
     "hobo_tensor_layout_info", "hobo_energy_noalloc", "hobo_aggregate",
+    "hobo_tt_build", "hobo_tt_free", "hobo_tt_info", "hobo_tt_cores", "hobo_tt_energy",
 ]
 
 
@@ -90,6 +91,11 @@ def _load():
     lib.hobo_energy.argtypes = [P, P, i64, i32, P, P]
     lib.hobo_energy_noalloc.argtypes = [P, P, i64, i32, P, P]
     lib.hobo_aggregate.argtypes = [i32, i64, P, P, i32, P, P, P]
+    lib.hobo_tt_build.argtypes = [P, ctypes.POINTER(P)]
+    lib.hobo_tt_free.argtypes = [P]
+    lib.hobo_tt_info.argtypes = [P, P, P, P, P]
+    lib.hobo_tt_cores.argtypes = [P, P, i64]
+    lib.hobo_tt_energy.argtypes = [P, P, i64, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
     lib.hobo_mlp_forward.argtypes = [P, P, i64, P, P]
@@ -399,3 +405,47 @@ def aggregate(n_vars: int, bits_host: np.ndarray, energies_host: np.ndarray):
                               _np_ptr(rep), _np_ptr(cnt)))
     u = int(nu[0])
     return rep[:u], cnt[:u]
+
+
+class TensorTrain:
+    """Owning handle of the TT form of a tensor (hobo_tt_build)."""
+
+    def __init__(self, t: Tensor):
+        h = ctypes.c_void_p()
+        _check(lib.hobo_tt_build(t.handle, ctypes.byref(h)))
+        self._h = h
+        order, n = np.zeros(1, np.int32), np.zeros(1, np.int32)
+        ranks = np.zeros(9, np.int32)
+        npar = np.zeros(1, np.int64)
+        _check(lib.hobo_tt_info(h, _np_ptr(order), _np_ptr(n), _np_ptr(ranks), _np_ptr(npar)))
+        self.order, self.n_vars = int(order[0]), int(n[0])
+        self.ranks = [int(r) for r in ranks[: self.order + 1]]
+        self.n_params = int(npar[0])
+
+    def cores(self) -> list:
+        flat = np.zeros(max(self.n_params, 1), dtype=np.float64)
+        _check(lib.hobo_tt_cores(self._h, _np_ptr(flat), len(flat)))
+        out, off = [], 0
+        for k in range(self.order):
+            shape = (self.ranks[k], self.n_vars, self.ranks[k + 1])
+            size = int(np.prod(shape))
+            out.append(flat[off:off + size].reshape(shape))
+            off += size
+        return out
+
+    def energy(self, x_bits, B: int, e_out, stream=None):
+        w = (self.n_vars + 63) // 64
+        if x_bits.numel() < w * B or e_out.numel() < B or e_out.element_size() != 8:
+            raise ValueError("x_bits [W][B] words and e_out [B] doubles")
+        _check(lib.hobo_tt_energy(self._h, _dev_ptr(x_bits), int(B), _dev_ptr(e_out), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.hobo_tt_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

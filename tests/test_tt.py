@@ -1,0 +1,91 @@
+"""The tensor-train form (Sec. VI.E-F): the library's host decomposition
+(one-sided Jacobi SVDs) against the oracle's (numpy SVD): same ranks (the
+printed 2, 3, 4, 4, 2 for the TSP tensor), cores that rebuild the dense
+paper-layout tensor, and energies through the cores equal to the term sums.
+The GPU contraction kernel is checked against the oracle's energies."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.tt as TT
+import workloads as W
+from paper_2407_19987_amd import hobo
+
+
+def _instances():
+    rng = np.random.default_rng(0)
+
+    def rand(seed, n, k, integer, dens=0.8):
+        r = np.random.default_rng(seed)
+        subs, co = [], []
+        for o in range(1, k + 1):
+            s = W.lex_subsets(n, o)
+            keep = r.random(len(s)) < dens
+            subs.append(s[keep])
+            v = r.integers(-5, 6, size=int(keep.sum())) if integer else \
+                r.standard_normal(int(keep.sum())).astype(np.float32).astype(np.float64)
+            co.append(v)
+        return W.subsets_to_terms(n, subs, co, integer)
+    del rng
+    return [("tsp", W.paper_tsp_intenc), ("pyth", W.paper_pythagorean), ("int3_n9", lambda: rand(1, 9, 3, True)),
+            ("real4_n6", lambda: rand(2, 6, 4, False)), ("real3_n16", lambda: rand(3, 16, 3, False, 0.5)),
+            ("int2_n24", lambda: rand(4, 24, 2, True, 0.3))]
+
+
+@pytest.mark.parametrize("name,make", _instances())
+def test_library_decomposition_matches_oracle(name, make):
+    terms = make()
+    c = oracle.canonicalize(terms)
+    h = oracle.paper_tensor(c).astype(np.float64)
+    _, ranks = TT.tt_svd(h)
+    tt = hobo.TensorTrain(hobo.Tensor.from_terms(terms))
+    assert tt.ranks == [1] + ranks + [1]
+    if name == "tsp":
+        assert tt.ranks == [1, 2, 3, 4, 4, 2, 1]
+    cores = tt.cores()
+    scale = max(np.abs(h).max(), 1.0)
+    assert np.abs(TT.tt_full(cores) - h).max() <= 1e-12 * scale * h.shape[0] ** 2
+    x = W.random_states(c.n_vars, 64, seed=5)
+    want = oracle.energy(c, W.pack_bits(x))
+    act = np.maximum(oracle.active_scale(c, W.pack_bits(x)), 1.0)
+    assert (np.abs(TT.tt_energies(cores, x) - want) <= 1e-11 * act * c.n_vars ** 2).all()
+
+
+def test_decomposition_limits():
+    # N^k above 2^24 entries (70^4) is refused before any work
+    p = W.RawPoly([((0, 1, 2, 3), 2), ((69,), -1)])
+    with pytest.raises(hobo.HoboError) as ei:
+        hobo.TensorTrain(hobo.Tensor.from_terms(W.poly_to_terms(70, p, True)))
+    assert ei.value.code == hobo.ERR_UNSUPPORTED
+    # a rank above the kernel's 32 is refused (a full-rank 40 x 40 quadratic form)
+    rng = np.random.default_rng(1)
+    s2 = W.lex_subsets(40, 2)
+    terms = W.subsets_to_terms(40, [np.arange(40).reshape(-1, 1), s2],
+                               [rng.integers(1, 9, size=40), rng.integers(-9, 10, size=len(s2))], True)
+    with pytest.raises(hobo.HoboError) as ei:
+        hobo.TensorTrain(hobo.Tensor.from_terms(terms))
+    assert ei.value.code == hobo.ERR_UNSUPPORTED
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,make", _instances())
+def test_gpu_tt_energies(name, make):
+    import torch
+
+    assert torch.cuda.is_available()
+    terms = make()
+    c = oracle.canonicalize(terms)
+    tt = hobo.TensorTrain(hobo.Tensor.from_terms(terms))
+    n = c.n_vars
+    x = W.all_states(n) if n <= 12 else W.random_states(n, 5000, seed=9)
+    bits = W.pack_bits(x)
+    xb = hobo.bits_to_device(bits)
+    e = torch.zeros(len(x), dtype=torch.float64, device="cuda")
+    tt.energy(xb, len(x), e)
+    torch.cuda.synchronize()
+    want = oracle.energy(c, bits)
+    act = np.maximum(oracle.active_scale(c, bits), 1.0)
+    got = e.cpu().numpy()
+    assert (np.abs(got - want) <= 1e-11 * act * n ** 2).all()
+    if c.integer:
+        np.testing.assert_array_equal(np.rint(got).astype(np.int64), want)
