@@ -499,3 +499,54 @@ def test_tt_energies_equal_the_definition(seed, n, k, integer):
     want = oracle.energy(c, W.pack_bits(x))
     scale = np.abs(np.asarray(c.weights, dtype=np.float64)).sum()
     assert np.abs(TT.tt_energies(cores, x) - want).max() <= 1e-12 * scale * n ** 2
+
+
+# ---------------------------------------------------------- gradient descent
+
+
+@pytest.mark.parametrize("seed,n,k,integer", [(1, 6, 3, False), (2, 5, 4, True), (3, 8, 2, False)])
+def test_gd_gradient_pins(seed, n, k, integer):
+    """The oracle's gradient of the multilinear extension: equal to central
+    finite differences (exact up to rounding, E being linear in each p_i);
+    equal to the local field at binary points; the extension equals the
+    energy at binary points."""
+    import oracle.gd as G
+
+    terms = _rand_int_instance(seed, n, k) if integer else _rand_real_instance(seed, n, k)
+    c = _canon(terms)
+    rng = np.random.default_rng(seed)
+    p = rng.random((7, n))
+    g = G.gradient(c, p)
+    h = 1e-3
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = h
+        fd = (G.extension(c, p + e) - G.extension(c, p - e)) / (2 * h)
+        np.testing.assert_allclose(g[:, i], fd, rtol=1e-9, atol=1e-9)
+    x = W.random_states(n, 9, seed=seed)
+    bits = W.pack_bits(x)
+    np.testing.assert_allclose(G.gradient(c, x.astype(np.float64)), oracle.fields(c, bits)[0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(G.extension(c, x.astype(np.float64)), oracle.energy(c, bits), rtol=0, atol=1e-12)
+
+
+def test_gd_step_by_hand():
+    """Two variables, E = 2 p0 - 3 p0 p1 + p1: g = (2 - 3 p1, 1 - 3 p0); one
+    projected step from (0.5, 0.9) with eta 0.5 gives (0.5 - 0.5 (2 - 2.7),
+    0.9 - 0.5 (1 - 1.5)) = (0.85, 1.15 -> 1.0); it rounds to (1, 1), E = 0."""
+    import oracle.gd as G
+
+    c = _canon(W.poly_to_terms(2, W.RawPoly([((0,), 2.0), ((0, 1), -3.0), ((1,), 1.0)]), False))
+    p = G.descend(c, np.array([[0.5, 0.9]]), 1, 0.5)
+    np.testing.assert_allclose(p, [[0.85, 1.0]], rtol=0, atol=1e-15)
+    x, e = G.round_and_score(c, p)
+    assert x.tolist() == [[1, 1]] and e.tolist() == [0.0]
+
+
+def test_gd_random_start_uses_philox_tag_3():
+    import oracle.gd as G
+
+    p = G.random_start(6, 2, seed=11)
+    for b in range(2):
+        for i in range(6):
+            word = _np_philox_word((b, 0, i // 4, 3), (11, 0), i % 4)
+            assert p[b, i] == (word >> 11) * 2.0 ** -53
