@@ -218,6 +218,7 @@ def main():
         eval_info = eval_rates(hobo, W, torch, dev, t, B)
         eval_info.update(int8_rates(hobo, W, torch, dev))
         eval_info.update(tt_rates(hobo, W, torch, dev))
+        eval_info.update(gd_rates(hobo, torch, dev, t, B))
 
     multi = None
     if args.mixed_instances > 0:
@@ -373,6 +374,33 @@ def tt_rates(hobo, W, torch, dev, bb=65536):
         out[f"tt_{name}_B{bb}"] = dict(us=us, evals_per_s=bb / (us * 1e-6), ranks=tt.ranks, fp64_tflops=tfl,
                                        frac_of_fp64_vector_peak=tfl / 78.6)
     return out
+
+
+def gd_rates(hobo, torch, dev, t, B, iters=100):
+    """Gradient-descent search (Sec. II.D.2) on the headline instance: B
+    replicas x `iters` projected FP64 steps, then rounding and exact
+    energies.  Gradient evaluations (replica-steps) per second and the FP64
+    rate of the record walk, sum_r r^2 nnz_r flops per replica-step (each
+    order-r monomial feeds r gradients, each r - 1 products and one sum),
+    against the FP64 vector peak (78.6 TFLOP/s)."""
+    n = t.n_vars
+    nnz = [int(v) for v in t.info().n_per_order]
+    p = torch.empty(n * B, dtype=torch.float64, device=dev)
+    x = torch.empty(((n + 63) // 64) * B, dtype=torch.int64, device=dev)
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    hobo.gd_batch(t, B, p, x, e, iterations=2, eta=0.05, seed=1)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    hobo.gd_batch(t, B, p, x, e, iterations=iters, eta=0.05, seed=1)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    flops = sum(r * r * c for r, c in enumerate(nnz)) * B * iters
+    return {f"gd_real3_n{n}_B{B}_{iters}steps": dict(
+        ms=ms, replica_steps_per_s=B * iters / (ms * 1e-3), fp64_tflops=flops / (ms * 1e-3) / 1e12,
+        frac_of_fp64_vector_peak=flops / (ms * 1e-3) / 1e12 / 78.6, best_rounded_energy=float(e.min().item()),
+        median_rounded_energy=float(e.median().item()))}
 
 
 def mixed(hobo, W, torch, dev, mi, mb, msw, tune):

@@ -278,6 +278,37 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances,
                               uint64_t* x_inout, uint64_t* best_x_out, void* best_e_out,
                               double* trace_out, int32_t launch_mode, void* stream);
 
+/* ------------------------------------------------------------- gradient descent */
+/* Gradient-descent search (Sec. II.D.2) on the multilinear extension of the
+ * energy, E(p) = sum_S w_S prod_{i in S} p_i for p in [0, 1]^N (equal to the
+ * energy at binary points), with
+ *   g_i(p) = dE/dp_i = sum_{S containing i} w_S prod_{j in S, j != i} p_j
+ * (the local field at binary points).  Each replica runs projected
+ * full-gradient steps p <- min(1, max(0, p - eta g(p))); the answer is the
+ * rounded state x_i = [p_i > 1/2] with its exact energy.  FP64, products
+ * and sums rounded separately, contributions summed in monomial order.
+ * Continuous points are device double [N][B] (variable-major: p_i of
+ * replica b at i * B + b). */
+typedef struct {
+  int32_t iterations;  /* steps, >= 0 */
+  int32_t init;        /* HOBO_INIT_RANDOM: p_i from Philox4x64-10 word i%4 at
+                          counter (b, 0, i/4, 3), key (seed, 0), as (r >> 11) 2^-53;
+                          HOBO_INIT_GIVEN: p_inout as passed */
+  double eta;          /* step size, finite, >= 0 */
+  uint64_t seed;
+} hobo_gd_params;
+
+/* g_out [N][B] = the gradient at p [N][B] (both device double). */
+hobo_status hobo_gd_gradient(const hobo_tensor* t, const double* p, int64_t B, double* g_out, void* stream);
+
+/* Run the steps on B replicas: p_inout (device double [N][B]) ends as the
+ * last point, x_out (device uint64 [W][B]) the rounded states, e_out (device
+ * int64[B] for integer tensors, double[B] otherwise) their exact energies
+ * (offset excluded).  Allocates a workspace of 8 N B bytes plus the energy
+ * pass's (stream-ordered). */
+hobo_status hobo_gd_batch(const hobo_tensor* t, int64_t B, const hobo_gd_params* params, double* p_inout,
+                          uint64_t* x_out, void* e_out, void* stream);
+
 /* ------------------------------------------------------------- tensor train */
 /* The tensor-train (TT) form of the HOBO tensor (Sec. VI.E-F): the dense
  * order-k tensor in the paper's layout, H[i_1..i_k] (a monomial of size r < k

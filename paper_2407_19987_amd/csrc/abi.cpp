@@ -1082,6 +1082,69 @@ hobo_status hobo_proposal_features(const hobo_tensor* tc, const uint64_t* x_bits
   return ok();
 }
 
+// ------------------------------------------------------------ gradient descent
+hobo_status hobo_gd_gradient(const hobo_tensor* tc, const double* p, int64_t B, double* g_out, void* stream) {
+  g_err.clear();
+  if (!tc || !p || !g_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (B < 1 || B > ((int64_t)1 << 40)) return fail(HOBO_ERR_INVALID_ARG, "B out of range");
+  if (hobo_status s = need_device()) return s;
+  hobo_tensor* t = const_cast<hobo_tensor*>(tc);
+  std::string err;
+  hobo::GDDev* gd;
+  if (int s = hobo::get_gd(&t->t, &gd, &err)) return fail(s, err);
+  hobo::GDArgs a{gd->d_ptr, gd->d_rec, t->t.n_vars, B, p, g_out, 0.0, 1, stream};
+  if (int s = hobo::launch_gd_step(a, &err)) return fail(s, err);
+  return ok();
+}
+
+hobo_status hobo_gd_batch(const hobo_tensor* tc, int64_t B, const hobo_gd_params* params, double* p_inout,
+                          uint64_t* x_out, void* e_out, void* stream) {
+  g_err.clear();
+  if (!tc || !params || !p_inout || !x_out || !e_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  const hobo_gd_params P = *params;
+  if (B < 1 || B > ((int64_t)1 << 31)) return fail(HOBO_ERR_INVALID_ARG, "B out of range");
+  if (P.iterations < 0) return fail(HOBO_ERR_INVALID_ARG, "iterations must be >= 0");
+  if (!(P.eta >= 0.0) || std::isinf(P.eta)) return fail(HOBO_ERR_INVALID_ARG, "eta must be finite and >= 0");
+  if (P.init != HOBO_INIT_RANDOM && P.init != HOBO_INIT_GIVEN) return fail(HOBO_ERR_INVALID_ARG, "unknown init");
+  if (hobo_status s = need_device()) return s;
+  hobo_tensor* t = const_cast<hobo_tensor*>(tc);
+  hipStream_t st = (hipStream_t)stream;
+  std::string err;
+  const int n = t->t.n_vars;
+  hobo::GDDev* gd;
+  if (int s = hobo::get_gd(&t->t, &gd, &err)) return fail(s, err);
+  hobo::TermsDev* td;
+  if (int s = hobo::get_terms(&t->t, &td, &err)) return fail(s, err);
+  if (P.init == HOBO_INIT_RANDOM)
+    if (int s = hobo::launch_gd_init(n, B, P.seed, p_inout, stream, &err)) return fail(s, err);
+  // ping-pong between the caller's buffer and a workspace; the term energies'
+  // workspace shares the allocation
+  const size_t pbytes = ((size_t)n * (size_t)B * 8 + 255) & ~(size_t)255;
+  const size_t wbytes = pbytes + hobo::term_workspace_bytes(&t->t, B);
+  void* work = nullptr;
+  if (hobo_status s = hip_status(hipMallocAsync(&work, wbytes, st), "hipMallocAsync")) return s;
+  double* other = static_cast<double*>(work);
+  double* cur = p_inout;
+  int rc = HOBO_OK;
+  for (int it = 0; it < P.iterations && rc == HOBO_OK; ++it) {
+    double* nxt = cur == p_inout ? other : p_inout;
+    hobo::GDArgs a{gd->d_ptr, gd->d_rec, n, B, cur, nxt, P.eta, 0, stream};
+    rc = hobo::launch_gd_step(a, &err);
+    cur = nxt;
+  }
+  if (rc == HOBO_OK && cur != p_inout)
+    rc = hip_status(hipMemcpyAsync(p_inout, cur, (size_t)n * (size_t)B * 8, hipMemcpyDeviceToDevice, st),
+                    "hipMemcpyAsync");
+  if (rc == HOBO_OK) rc = hobo::launch_gd_round(n, B, p_inout, x_out, stream, &err);
+  if (rc == HOBO_OK) {
+    hobo::TermArgs ta{td, &t->t, x_out, B, e_out, static_cast<char*>(work) + pbytes, stream};
+    rc = hobo::launch_term_energy(ta, &err);
+  }
+  (void)hipFreeAsync(work, st);
+  if (rc != HOBO_OK) return err.empty() ? rc : fail(rc, err);
+  return ok();
+}
+
 // ------------------------------------------------------------ tensor train
 struct hobo_tt {
   std::unique_ptr<hobo::TTDev> tt;

@@ -167,6 +167,7 @@ struct Tensor {
   std::mutex mu;
   std::map<int, std::unique_ptr<Packed>> packed;  // key = mode*16 + prec
   std::unique_ptr<TermsDev> terms;
+  std::unique_ptr<struct GDDev> gd;  // gradient-descent records (built on first use)
   double* d_row_norm = nullptr;  // device copy of row_norm (uploaded on first use)
   // autotuned launch shapes (hobo_autotune): key = (kernel << 16) | (prec << 8) | ceil(log2 B)
   std::map<uint32_t, int> tuned;
@@ -210,6 +211,37 @@ int tt_decompose(const Tensor* t, std::unique_ptr<TTDev>* out, std::string* err)
 int tt_upload(TTDev* tt, std::string* err);
 int launch_tt_energy(const TTDev* tt, const uint64_t* bits, int64_t B, double* e_out, void* stream,
                      std::string* err);
+
+// gd.cpp / gd_kernels.hip -- projected gradient descent on the multilinear
+// extension.  Per variable i, one record per monomial S containing i: its
+// weight and the other variables of S (ascending), in monomial order.
+struct GDRec {
+  double w;
+  uint8_t n;       // other variables (|S| - 1)
+  uint8_t o[7];
+};
+struct GDDev {
+  int n_vars = 0;
+  int32_t* d_ptr = nullptr;  // [n_vars + 1] record offsets per variable
+  GDRec* d_rec = nullptr;
+  size_t bytes = 0;
+  ~GDDev();
+};
+int get_gd(Tensor* t, GDDev** out, std::string* err);
+struct GDArgs {
+  const int32_t* ptr;   // device copies of the GDDev arrays
+  const GDRec* rec;
+  int n_vars;
+  int64_t B;
+  const double* p_in;   // [N][B]
+  double* p_out;        // [N][B]: the projected step (mode 0) or the gradient (mode 1)
+  double eta;
+  int mode;
+  void* stream;
+};
+int launch_gd_step(const GDArgs& a, std::string* err);
+int launch_gd_init(int n_vars, int64_t B, uint64_t seed, double* p, void* stream, std::string* err);
+int launch_gd_round(int n_vars, int64_t B, const double* p, uint64_t* x, void* stream, std::string* err);
 
 // results.cpp -- unique states of a batch (host buffers), ordered by energy
 // then by the bit sequence x_0, x_1, ...; per unique state the first replica

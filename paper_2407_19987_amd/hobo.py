@@ -41,6 +41,7 @@ EXPORTS = [
     "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features", "hobo_autotune",
     "hobo_tensor_layout_info", "hobo_energy_noalloc", "hobo_aggregate",
     "hobo_tt_build", "hobo_tt_free", "hobo_tt_info", "hobo_tt_cores", "hobo_tt_energy",
+    "hobo_gd_gradient", "hobo_gd_batch",
 ]
 
 
@@ -70,6 +71,11 @@ class AnnealParams(ctypes.Structure):
                 ("tau", ctypes.c_float), ("p_floor", ctypes.c_float)]
 
 
+class GDParams(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("init", ctypes.c_int32), ("eta", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
 class MlpTrainParams(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
@@ -96,6 +102,8 @@ def _load():
     lib.hobo_tt_info.argtypes = [P, P, P, P, P]
     lib.hobo_tt_cores.argtypes = [P, P, i64]
     lib.hobo_tt_energy.argtypes = [P, P, i64, P, P]
+    lib.hobo_gd_gradient.argtypes = [P, P, i64, P, P]
+    lib.hobo_gd_batch.argtypes = [P, i64, ctypes.POINTER(GDParams), P, P, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
     lib.hobo_mlp_forward.argtypes = [P, P, i64, P, P]
@@ -449,3 +457,21 @@ class TensorTrain:
             self.close()
         except Exception:
             pass
+
+
+def gd_gradient(t: Tensor, p, B: int, g_out, stream=None):
+    """hobo_gd_gradient: p, g_out device float64 [N][B]."""
+    if p.numel() < t.n_vars * B or g_out.numel() < t.n_vars * B or p.element_size() != 8:
+        raise ValueError("p and g_out must hold [N][B] doubles")
+    _check(lib.hobo_gd_gradient(t.handle, _dev_ptr(p), int(B), _dev_ptr(g_out), _stream(stream)))
+
+
+def gd_batch(t: Tensor, B: int, p_inout, x_out, e_out, *, iterations: int, eta: float, seed: int = 0,
+             init: int = INIT_RANDOM, stream=None):
+    """hobo_gd_batch: p_inout device float64 [N][B], x_out [W][B] words, e_out [B]."""
+    w = (t.n_vars + 63) // 64
+    if p_inout.numel() < t.n_vars * B or x_out.numel() < w * B or e_out.numel() < B:
+        raise ValueError("buffer sizes")
+    prm = GDParams(int(iterations), int(init), float(eta), int(seed))
+    _check(lib.hobo_gd_batch(t.handle, int(B), ctypes.byref(prm), _dev_ptr(p_inout), _dev_ptr(x_out),
+                             _dev_ptr(e_out), _stream(stream)))
