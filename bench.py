@@ -58,6 +58,11 @@ def w_energy(n: int, k: int) -> int:
     return 2 * sum(math.comb(n, r) for r in range(1, k + 1))
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -84,7 +89,9 @@ def main():
     ap.add_argument("--mixed-instances", type=int, default=16,
                     help="instances of the mixed family for the persistent-vs-per-instance comparison (0: skip)")
     ap.add_argument("--mixed-full", action="store_true",
-                    help="the mixed workload at full size: 256 instances x 1024 replicas x 500 sweeps")
+                    help="the mixed workload at its full size: 256 instances x 1024 replicas")
+    ap.add_argument("--mixed-sweeps", type=int, default=500,
+                    help="sweeps of the --mixed-full runs (the time of 500 is extrapolated linearly when fewer)")
     ap.add_argument("--ttt-seeds", type=int, default=0,
                     help="held-out instances for the learned-vs-plain time-to-target comparison (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -223,7 +230,14 @@ def main():
     multi = None
     if args.mixed_instances > 0:
         multi = mixed(hobo, W, torch, dev, args.mixed_instances, 256, 100, tune=False)
-    mixed_full = mixed(hobo, W, torch, dev, 256, 1024, 500, tune=True) if args.mixed_full else None
+    mixed_full = None
+    if args.mixed_full:
+        mixed_full = mixed(hobo, W, torch, dev, 256, 1024, args.mixed_sweeps, tune=True)
+        if args.mixed_sweeps != 500:  # every sweep costs the same: linear in the sweep count
+            k = 500 / args.mixed_sweeps
+            mixed_full["extrapolated_to_500_sweeps"] = {
+                key: mixed_full[key] * k for key in ("per_instance_ms", "persistent_graph_ms", "tuned_graph_ms")
+                if key in mixed_full}
     ttt = ttt_eval(hobo, W, torch, dev, args.ttt_seeds, S, PREC_OF[args.precision]) if args.ttt_seeds > 0 else None
 
     cpu = None
@@ -410,9 +424,12 @@ def mixed(hobo, W, torch, dev, mi, mb, msw, tune):
     `tune`, also the persistent launch after hobo_autotune of each instance's
     annealer shape against the default shapes."""
     th0 = time.perf_counter()
-    mts = [hobo.Tensor.from_terms(W.cfg_mixed_instance(0, i)) for i in range(mi)]
-    for mt in mts:
-        mt.prepare(hobo.FN_ANNEAL, 1 << PREC_OF["fp32"])
+    mts = []
+    for i in range(mi):
+        mts.append(hobo.Tensor.from_terms(W.cfg_mixed_instance(0, i)))
+        mts[-1].prepare(hobo.FN_ANNEAL, 1 << PREC_OF["fp32"])
+        if (i + 1) % 32 == 0:
+            progress(f"mixed instances built and packed: {i + 1} of {mi}")
     host_s = time.perf_counter() - th0
     words = sum(((mt.n_vars + 63) // 64) * mb for mt in mts)
     mx = torch.zeros(words, dtype=torch.int64, device=dev)
@@ -422,6 +439,7 @@ def mixed(hobo, W, torch, dev, mi, mb, msw, tune):
     res = {}
 
     def run(name, mode, reps):
+        progress(f"mixed {mi} x {mb} x {msw}: {name}")
         kw = dict(sweeps=msw, t_start=T0, t_end=T1, seed=3, precision=PREC_OF["fp32"], trace_out=mtr,
                   launch_mode=mode)
         hobo.anneal_batch(mts, [mb] * mi, mx, mbx, mbe, **kw)
@@ -489,6 +507,8 @@ def ttt_eval(hobo, W, torch, dev, n_seeds, S, prec):
     tr = torch.empty(win, dtype=torch.float64, device=dev)
     rows = []
     for k in range(n_seeds):
+        if k % 8 == 0:
+            progress(f"time to target: held-out instance {k} of {n_seeds}")
         tk = hobo.Tensor.from_terms(W.cfg_real3(seed=10000 + k, n=N_VARS))
         tk.prepare(hobo.FN_ANNEAL | hobo.FN_FIELDS, 1 << prec)
         curves = {}

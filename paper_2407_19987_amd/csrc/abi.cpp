@@ -1092,7 +1092,7 @@ hobo_status hobo_gd_gradient(const hobo_tensor* tc, const double* p, int64_t B, 
   std::string err;
   hobo::GDDev* gd;
   if (int s = hobo::get_gd(&t->t, &gd, &err)) return fail(s, err);
-  hobo::GDArgs a{gd->d_ptr, gd->d_rec, t->t.n_vars, B, p, g_out, 0.0, 1, stream};
+  hobo::GDArgs a{gd->d_ptr, gd->d_rec, t->t.n_vars, B, p, g_out, 0.0, 1, t->t.order, stream};
   if (int s = hobo::launch_gd_step(a, &err)) return fail(s, err);
   return ok();
 }
@@ -1128,7 +1128,7 @@ hobo_status hobo_gd_batch(const hobo_tensor* tc, int64_t B, const hobo_gd_params
   int rc = HOBO_OK;
   for (int it = 0; it < P.iterations && rc == HOBO_OK; ++it) {
     double* nxt = cur == p_inout ? other : p_inout;
-    hobo::GDArgs a{gd->d_ptr, gd->d_rec, n, B, cur, nxt, P.eta, 0, stream};
+    hobo::GDArgs a{gd->d_ptr, gd->d_rec, n, B, cur, nxt, P.eta, 0, t->t.order, stream};
     rc = hobo::launch_gd_step(a, &err);
     cur = nxt;
   }

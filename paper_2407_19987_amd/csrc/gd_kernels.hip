@@ -19,9 +19,13 @@
 
 namespace hobo {
 
-constexpr int kGDWaves = 4;       // waves per work-group
-constexpr int kGDSliceVars = 16;  // variables per work-group (grid.y covers N)
+constexpr int kGDWaves = 4;      // waves per work-group
+constexpr int kGDSliceVars = 8;  // variables per work-group (grid.y covers N)
 
+// MAXO: largest monomial order of the tensor (records carry up to MAXO - 1
+// other variables), so the product loop has a fixed trip count with
+// wave-uniform guards
+template <int MAXO>
 __global__ __launch_bounds__(64 * kGDWaves) void gd_step_kernel(GDArgs a) {
   extern __shared__ double sp[];  // [N][64]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -38,13 +42,45 @@ __global__ __launch_bounds__(64 * kGDWaves) void gd_step_kernel(GDArgs a) {
   const int i0 = blockIdx.y * kGDSliceVars;
   const int i1 = i0 + kGDSliceVars < N ? i0 + kGDSliceVars : N;
   for (int i = i0 + w; i < i1; i += kGDWaves) {
-    const int r0 = gld(a.ptr + i), r1 = gld(a.ptr + i + 1);
+    const int r0 = __builtin_amdgcn_readfirstlane(gld(a.ptr + i));
+    const int r1 = __builtin_amdgcn_readfirstlane(gld(a.ptr + i + 1));
     double g = 0.0;
-    for (int r = r0; r < r1; ++r) {
-      const GDRec rec = a.rec[r];
-      double prod = rec.w;
-      for (int q = 0; q < rec.n; ++q) prod = __dmul_rn(prod, sp[rec.o[q] * 64 + lane]);
-      g = __dadd_rn(g, prod);
+    // 64 records per round: lane l loads record r + l (one coalesced load,
+    // the next round's issued before this one is used); each record's fields
+    // are then broadcast from its lane into scalar registers
+    auto load = [&](int r) {
+      u4 v = u4{0u, 0u, 0u, 0u};
+      if (r + lane < r1) v = gld(reinterpret_cast<const u4*>(a.rec) + r + lane);
+      return v;
+    };
+    // product of record k of the round: its weight times the other variables' p
+    auto term = [&](const u4& cur, int k) {
+      const unsigned wlo = __builtin_amdgcn_readlane(cur[0], k), whi = __builtin_amdgcn_readlane(cur[1], k);
+      const unsigned no = __builtin_amdgcn_readlane(cur[2], k), o47 = __builtin_amdgcn_readlane(cur[3], k);
+      double prod = __hiloint2double((int)whi, (int)wlo);
+      const int nn = (int)(no & 0xFFu);
+#pragma unroll
+      for (int q = 0; q < MAXO - 1; ++q) {
+        if (q < nn) {
+          const unsigned o = q < 3 ? (no >> (8 * (q + 1))) & 0xFFu : (o47 >> (8 * (q - 3))) & 0xFFu;
+          prod = __dmul_rn(prod, sp[o * 64 + lane]);
+        }
+      }
+      return prod;
+    };
+    u4 cur = load(r0);
+    for (int r = r0; r < r1; r += 64) {
+      const u4 nxt = load(r + 64);
+      const int cnt = r1 - r < 64 ? r1 - r : 64;
+      int k = 0;
+      // four records at a time: their LDS reads overlap; the sum keeps the
+      // record order
+      for (; k + 4 <= cnt; k += 4) {
+        const double t0 = term(cur, k), t1 = term(cur, k + 1), t2 = term(cur, k + 2), t3 = term(cur, k + 3);
+        g = __dadd_rn(__dadd_rn(__dadd_rn(__dadd_rn(g, t0), t1), t2), t3);
+      }
+      for (; k < cnt; ++k) g = __dadd_rn(g, term(cur, k));
+      cur = nxt;
     }
     if (live) {
       if (a.mode == 1) {
@@ -91,11 +127,25 @@ int launch_gd_step(const GDArgs& a, std::string* err) {
   static std::once_flag once;
   static hipError_t attr = hipSuccess;
   std::call_once(once, [] {
-    attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gd_step_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxVars * 64 * sizeof(double)));
+    const int bytes = (int)(kMaxVars * 64 * sizeof(double));
+    const void* fns[4] = {reinterpret_cast<const void*>(&gd_step_kernel<2>),
+                          reinterpret_cast<const void*>(&gd_step_kernel<3>),
+                          reinterpret_cast<const void*>(&gd_step_kernel<4>),
+                          reinterpret_cast<const void*>(&gd_step_kernel<kMaxOrder>)};
+    for (const void* f : fns)
+      if (attr == hipSuccess) attr = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   });
   if (int s = hip_fail(attr, err, "hipFuncSetAttribute(gradient step LDS)")) return s;
-  hipLaunchKernelGGL(gd_step_kernel, grid, dim3(64 * kGDWaves), lds, (hipStream_t)a.stream, a);
+  const dim3 blk(64 * kGDWaves);
+  const hipStream_t st = (hipStream_t)a.stream;
+  if (a.max_order <= 2)
+    hipLaunchKernelGGL(gd_step_kernel<2>, grid, blk, lds, st, a);
+  else if (a.max_order == 3)
+    hipLaunchKernelGGL(gd_step_kernel<3>, grid, blk, lds, st, a);
+  else if (a.max_order == 4)
+    hipLaunchKernelGGL(gd_step_kernel<4>, grid, blk, lds, st, a);
+  else
+    hipLaunchKernelGGL(gd_step_kernel<kMaxOrder>, grid, blk, lds, st, a);
   return hip_fail(hipGetLastError(), err, "gradient step launch");
 }
 

@@ -237,6 +237,7 @@ struct GDArgs {
   double* p_out;        // [N][B]: the projected step (mode 0) or the gradient (mode 1)
   double eta;
   int mode;
+  int max_order;        // largest monomial order of the tensor
   void* stream;
 };
 int launch_gd_step(const GDArgs& a, std::string* err);
