@@ -219,9 +219,14 @@ typedef struct {
   int32_t proposal;    /* METROPOLIS, MASKED (attempt masks) or LEARNED (network) */
   const uint8_t* attempt; /* MASKED: device uint8 [ceil(B/16)][sweeps][N] per instance,
                              concatenated; 1 = the 16-replica group visits the bit */
-  int32_t waves_per_block; /* waves sharing 16 replicas (1, 2, 4, 8, 16); 0 = default.
-                              The per-bit kernel uses at most 8, the blocked one at
-                              least 2.  Results do not depend on it. */
+  int32_t waves_per_block; /* waves sharing 16 replicas (1, 2, 4, 8, 16); 0 = default
+                              (the autotuned width, else 16 up to 256 groups of 16
+                              replicas in the call, 8 above).  The per-bit kernel uses
+                              at most 8, the blocked one at least 2.  Integer results
+                              do not depend on it; for real coefficients the blocked
+                              kernel's width sets how its FP32 partial fields are
+                              grouped, so decisions within rounding of a tie may
+                              differ between widths. */
   int32_t algorithm;   /* HOBO_ANNEAL_AUTO | SLABS | BLOCKS */
   int32_t first_sweep; /* this call runs sweeps first_sweep .. first_sweep+sweeps-1 */
   int32_t schedule_sweeps; /* L, length of the whole schedule; 0 = sweeps (first_sweep
@@ -267,7 +272,8 @@ typedef struct {
  *  launch_mode : PER_INSTANCE (one launch sequence per instance),
  *                PERSISTENT (one persistent launch over all instances), or
  *                GRAPH (the persistent sequence captured once in a hipGraph
- *                and launched from it) -- identical results
+ *                and launched from it) -- the same kernels and widths in all
+ *                three, so identical results
  * The library keeps the device setup of recent calls (tables, a workspace of
  * up to about 1 GiB of Metropolis uniforms per call, the captured graph), keyed
  * by every argument including the buffer pointers, so a repeated call only

@@ -882,6 +882,14 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     // persistent modes each part runs most expensive instances first
     std::vector<hobo::AnnealItem> items;
     auto cost = [&](int j) { return (int64_t)pks[(size_t)j]->ntiles; };
+    // blocked-kernel width: set by the whole call's item count in every
+    // launch mode, so that the modes run the same kernels (the width sets
+    // how the FP32 partial fields are grouped, so real-valued results
+    // depend on it)
+    int64_t n_blk_items = 0;
+    for (int j = 0; j < n_instances; ++j)
+      if (blocked[(size_t)j]) n_blk_items += (int64_t)items_of[(size_t)j].size();
+    const int call_nw_blk = blk_waves(n_blk_items);
     if (launch_mode == HOBO_LAUNCH_PER_INSTANCE) {
       for (int j = 0; j < n_instances; ++j) {
         hobo::AnnealPlan pl = base_plan();
@@ -891,7 +899,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
         const int nt = (int)items_of[(size_t)j].size();
         if (blocked[(size_t)j]) {
           pl.n_blk = nt;
-          pl.nw_blk = blk_waves(nt);
+          pl.nw_blk = call_nw_blk;
         } else {
           pl.n_slab = nt;
           hobo::anneal_shape((tensors[j]->t.n_vars + 15) / 16, slab_waves, &pl.ct, &pl.nw);
@@ -912,7 +920,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
             items.insert(items.end(), items_of[(size_t)j].begin(), items_of[(size_t)j].end());
             (pass == 0 ? pl.n_blk : pl.n_slab) += (int)items_of[(size_t)j].size();
           }
-      pl.nw_blk = blk_waves(pl.n_blk);
+      pl.nw_blk = call_nw_blk;
       // slab kernel shape: widest instance decides (all share one launch)
       int maxT = 1;
       for (int j = 0; j < n_instances; ++j)

@@ -369,3 +369,17 @@ def test_real_trajectory_decisions(env, prec, algo):
         x = g["final_bits"]
     print(f"replica-sweeps checked exactly: {exact} of {B * S}; near-tie divergences: {ties}; moved: {moved}")
     assert exact >= 0.6 * B * S and moved >= 0.5 * B * S
+
+
+def test_multi_instance_launch_modes_agree_real(env):
+    """Real coefficients: the three launch modes run the same kernels with the
+    same widths, so even the FP32 rounding of every flip change is the same
+    and the results are identical, bit for bit."""
+    hobo, _ = env
+    specs = [(W.cfg_real3(seed=31, n=40), 48), (W.cfg_real3(seed=32, n=70), 80), (W.cfg_mixed_instance(0, 3), 32)]
+    tensors = [hobo.Tensor.from_terms(s) for s, _ in specs]
+    reps = [b for _, b in specs]
+    out = {mode: run_gpu(env, tensors, reps, 12, 3.0, 0.2, seed=5, prec=0, mode=mode) for mode in (0, 1, 2)}
+    for j in range(len(specs)):
+        for mode in (1, 2):
+            assert_same(out[mode][j], out[0][j])
