@@ -94,6 +94,8 @@ def main():
                     help="sweeps of the --mixed-full runs (the time of 500 is extrapolated linearly when fewer)")
     ap.add_argument("--ttt-seeds", type=int, default=0,
                     help="held-out instances for the learned-vs-plain time-to-target comparison (0: skip)")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="only the evaluation kernels' rates (energy and fields at B=4096 and 65536, INT8x4, TT)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (scale for the HBM traffic counters)")
     args = ap.parse_args()
@@ -121,6 +123,12 @@ def main():
     B, S = args.replicas, args.sweeps
     terms = W.cfg_real3(seed=0, n=N_VARS)
     t = hobo.Tensor.from_terms(terms)
+    if args.eval_only:
+        t.prepare(hobo.FN_ENERGY | hobo.FN_FIELDS, sum(1 << p for p in PREC_OF.values()))
+        info = eval_rates(hobo, W, torch, dev, t, B)
+        info.update(int8_rates(hobo, W, torch, dev))
+        print(json.dumps({"eval_kernels": info}))
+        return
     t.prepare(hobo.FN_ENERGY | hobo.FN_FIELDS | hobo.FN_ANNEAL, sum(1 << p for p in PREC_OF.values()))
     W_ = (N_VARS + 63) // 64
     xs = hobo.bits_to_device(W.pack_bits(W.random_states(N_VARS, B, seed=1000)))
@@ -535,7 +543,7 @@ def ttt_eval(hobo, W, torch, dev, n_seeds, S, prec):
             row[name] = hit[0] if hit else None
             row[name + "_total_ms"] = curve[-1][0]
         rows.append(row)
-    out = {"seeds": n_seeds, "window_sweeps": win, "precision": prec, "learned": info}
+    out = {"seeds": n_seeds, "window_sweeps": win, "precision": prec, "training": info}
     for name in ("plain", "learned"):
         v = np.array([r[name] for r in rows if r[name] is not None])
         out[name] = dict(reached=int(len(v)), median_ms=float(np.median(v)) if len(v) else None,
