@@ -401,14 +401,17 @@ typedef struct {
 hobo_status hobo_mlp_train(float* state, const float* feats, const float* labels, int64_t M,
                            const hobo_mlp_train_params* tp, float* loss_trace, void* stream);
 
-/* Features of every bit of B states: feats_out [B][N][3] FP32 =
- * (x_i, beta dE_i, beta ||H_i||) with dE from hobo_local_fields (de: device
- * [B][N], int64 for integer tensors, else FP32) and ||H_i|| the Euclidean norm
- * of the coefficients of all monomials containing i.  With x_after (device
- * [W][B]) and labels_out (device FP32 [B][N]) also the transition labels
- * [x_i != x_after_i]. */
+/* Features of every bit of B states before sweep `sweep` of an annealing
+ * schedule: feats_out [B][N][3] FP32 = (x_i, beta dE_i, beta ||H_i||) with
+ * beta = 1 / T_sweep of the geometric schedule t_start -> t_end over
+ * schedule_sweeps sweeps (the schedule hobo_anneal_batch uses), dE from
+ * hobo_local_fields (de: device [B][N], int64 for integer tensors, else
+ * FP32) and ||H_i|| the Euclidean norm of the coefficients of all monomials
+ * containing i.  With x_after (device [W][B]) and labels_out (device FP32
+ * [B][N]) also the transition labels [x_i != x_after_i]. */
 hobo_status hobo_proposal_features(const hobo_tensor* t, const uint64_t* x_bits, const uint64_t* x_after, int64_t B,
-                                   const void* de, double beta, float* feats_out, float* labels_out, void* stream);
+                                   const void* de, double t_start, double t_end, int32_t sweep,
+                                   int32_t schedule_sweeps, float* feats_out, float* labels_out, void* stream);
 
 /* ------------------------------------------------------------- autotuning */
 /* Times every launch shape of the kernels in fn_mask (1 energy: 16*rt

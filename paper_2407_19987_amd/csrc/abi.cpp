@@ -45,6 +45,13 @@ hobo_status need_device() {
   return HOBO_OK;
 }
 
+// inverse temperature of sweep s of an L-sweep geometric schedule,
+// T_s = T_0 (T_end / T_0)^(s / (L - 1)) (Sec. II.D.1 reading), beta_s = 1 / T_s
+double schedule_beta(double t_start, double t_end, int64_t s, int64_t L) {
+  const double T = L == 1 ? t_start : t_start * std::pow(t_end / t_start, (double)s / (double)(L - 1));
+  return 1.0 / T;
+}
+
 bool valid_prec(int p) { return p >= HOBO_PREC_FP32 && p <= HOBO_PREC_FP16X2; }
 
 // Tile shape of the evaluation kernels: 16*rt replicas x 16*ct columns per
@@ -682,11 +689,7 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
 
   // inverse temperatures of this call's sweeps
   std::vector<double> beta((size_t)std::max(S, 1));
-  for (int s = 0; s < S; ++s) {
-    const int64_t sg = (int64_t)P.first_sweep + s;
-    double T = L == 1 ? P.t_start : P.t_start * std::pow(P.t_end / P.t_start, (double)sg / (double)(L - 1));
-    beta[(size_t)s] = 1.0 / T;
-  }
+  for (int s = 0; s < S; ++s) beta[(size_t)s] = schedule_beta(P.t_start, P.t_end, P.first_sweep + s, L);
   const int init_random = P.init == HOBO_INIT_RANDOM ? 1 : 0;
   // Tuned annealer width of the call's kernel of each kind (1 blocked, 0
   // per-bit): the hobo_autotune result of its costliest instance (stored
@@ -1071,12 +1074,17 @@ hobo_status hobo_mlp_grad(const float* params, const float* feats, const float* 
 }
 
 hobo_status hobo_proposal_features(const hobo_tensor* tc, const uint64_t* x_bits, const uint64_t* x_after, int64_t B,
-                                   const void* de, double beta, float* feats_out, float* labels_out, void* stream) {
+                                   const void* de, double t_start, double t_end, int32_t sweep,
+                                   int32_t schedule_sweeps, float* feats_out, float* labels_out, void* stream) {
   g_err.clear();
   if (!tc || !x_bits || !de || !feats_out) return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
   if (labels_out && !x_after) return fail(HOBO_ERR_INVALID_ARG, "labels need x_after");
   if (B < 1 || B > (int64_t)1 << 40) return fail(HOBO_ERR_INVALID_ARG, "B out of range");
-  if (!std::isfinite(beta)) return fail(HOBO_ERR_INVALID_ARG, "beta must be finite");
+  if (!(t_start > 0.0) || !(t_end > 0.0) || !std::isfinite(t_start) || !std::isfinite(t_end))
+    return fail(HOBO_ERR_INVALID_ARG, "temperatures must be finite and > 0");
+  if (schedule_sweeps < 1 || sweep < 0 || sweep >= schedule_sweeps)
+    return fail(HOBO_ERR_INVALID_ARG, "sweep must lie in [0, schedule_sweeps)");
+  const double beta = schedule_beta(t_start, t_end, sweep, schedule_sweeps);
   if (hobo_status s = need_device()) return s;
   hobo_tensor* t = const_cast<hobo_tensor*>(tc);
   std::string err;

@@ -110,7 +110,7 @@ def _load():
     lib.hobo_mlp_grad.argtypes = [P, P, P, i64, P, P, P]
     lib.hobo_autotune.argtypes = [P, P, i64, i32, i32, P, P]
     lib.hobo_mlp_train.argtypes = [P, P, P, i64, ctypes.POINTER(MlpTrainParams), P, P]
-    lib.hobo_proposal_features.argtypes = [P, P, P, i64, P, ctypes.c_double, P, P, P]
+    lib.hobo_proposal_features.argtypes = [P, P, P, i64, P, ctypes.c_double, ctypes.c_double, i32, i32, P, P, P]
     lib.hobo_timing_enable.argtypes = [i32]
     lib.hobo_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
@@ -347,9 +347,10 @@ def mlp_train(state, feats, labels, *, batch: int, epochs: int, lr: float, beta1
                               _dev_ptr(loss_trace) if loss_trace is not None else None, _stream(stream)))
 
 
-def proposal_features(t: Tensor, x_bits, B: int, de, beta: float, feats_out, x_after=None, labels_out=None,
-                      stream=None):
-    """hobo_proposal_features: feats_out [B][N][3] (and transition labels)."""
+def proposal_features(t: Tensor, x_bits, B: int, de, feats_out, *, t_start: float, t_end: float, sweep: int,
+                      schedule_sweeps: int, x_after=None, labels_out=None, stream=None):
+    """hobo_proposal_features: feats_out [B][N][3] before sweep `sweep` of the
+    schedule (and transition labels)."""
     _check_bits(t, x_bits, B)
     n = t.n_vars
     if feats_out.numel() < 3 * B * n or de.numel() < B * n:
@@ -357,7 +358,8 @@ def proposal_features(t: Tensor, x_bits, B: int, de, beta: float, feats_out, x_a
     if labels_out is not None and (x_after is None or labels_out.numel() < B * n):
         raise ValueError("labels need x_after and B*N values")
     _check(lib.hobo_proposal_features(t.handle, _dev_ptr(x_bits), _dev_ptr(x_after) if x_after is not None else None,
-                                      int(B), _dev_ptr(de), float(beta), _dev_ptr(feats_out),
+                                      int(B), _dev_ptr(de), float(t_start), float(t_end), int(sweep),
+                                      int(schedule_sweeps), _dev_ptr(feats_out),
                                       _dev_ptr(labels_out) if labels_out is not None else None, _stream(stream)))
 
 

@@ -18,12 +18,6 @@ import numpy as np
 from . import hobo
 
 
-def inverse_temperature(s: int, sweeps: int, t_start: float, t_end: float) -> float:
-    """beta_s = 1 / T_s of the geometric schedule T_s = T_0 (T_1/T_0)^(s/(S-1))."""
-    t = t_start if sweeps == 1 else t_start * (t_end / t_start) ** (s / (sweeps - 1))
-    return 1.0 / t
-
-
 def record_transitions(t: "hobo.Tensor", replicas: int, sweeps: int, t_start: float, t_end: float, seed: int,
                        record: list, precision: int = hobo.PREC_BF16X2):
     """Transitions of a plain annealing run: for each sweep index in
@@ -54,8 +48,8 @@ def record_transitions(t: "hobo.Tensor", replicas: int, sweeps: int, t_start: fl
         x_before = x.clone()
         hobo.anneal_batch(t, b, x, bx, be, sweeps=1, init=hobo.INIT_GIVEN, first_sweep=r, continue_best=True,
                           **common)
-        hobo.proposal_features(t, x_before, b, de, inverse_temperature(r, sweeps, t_start, t_end), feats[k],
-                               x_after=x, labels_out=labels[k])
+        hobo.proposal_features(t, x_before, b, de, feats[k], t_start=t_start, t_end=t_end, sweep=r,
+                               schedule_sweeps=sweeps, x_after=x, labels_out=labels[k])
         s = r + 1
     return feats.reshape(-1, 3).contiguous(), labels.reshape(-1).contiguous()
 

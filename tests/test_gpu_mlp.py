@@ -113,7 +113,9 @@ def test_features_and_labels(env, integer):
     terms = W.cfg_int3(seed=7, n=21) if integer else W.cfg_real3(seed=7, n=40)
     c = oracle.canonicalize(terms)
     t = hobo.Tensor.from_terms(terms)
-    n, B, beta = c.n_vars, 77, 0.37
+    # sweep 3 of a 9-sweep 4.0 -> 0.5 schedule: the library computes beta itself
+    n, B, T0, T1, sw, L = c.n_vars, 77, 4.0, 0.5, 3, 9
+    beta = 1.0 / oracle.schedule(T0, T1, L)[sw]
     x = W.random_states(n, B, seed=8)
     xa = W.random_states(n, B, seed=9)
     xb, xab = hobo.bits_to_device(W.pack_bits(x)), hobo.bits_to_device(W.pack_bits(xa))
@@ -121,7 +123,8 @@ def test_features_and_labels(env, integer):
     hobo.local_fields(t, xb, B, hobo.PREC_FP32, de)
     feats = torch.empty((B, n, 3), dtype=torch.float32, device="cuda")
     labels = torch.empty((B, n), dtype=torch.float32, device="cuda")
-    hobo.proposal_features(t, xb, B, de, beta, feats, x_after=xab, labels_out=labels)
+    hobo.proposal_features(t, xb, B, de, feats, t_start=T0, t_end=T1, sweep=sw, schedule_sweeps=L, x_after=xab,
+                           labels_out=labels)
     got = feats.cpu().numpy()
     want = M.features(c, W.pack_bits(x), beta)
     np.testing.assert_array_equal(labels.cpu().numpy(), (x != xa).astype(np.float32))
