@@ -383,3 +383,37 @@ def test_multi_instance_launch_modes_agree_real(env):
     for j in range(len(specs)):
         for mode in (1, 2):
             assert_same(out[mode][j], out[0][j])
+
+
+def test_n256_anneal_trajectory(env):
+    """The largest instance size (N = 256, four words per state) in the
+    blocked annealer (order 3, integer, FP16X2) and the per-bit one: the
+    oracle's chain exactly."""
+    hobo, _ = env
+    terms = _int_instance(257, 256, 3, lo=-3, hi=3, dens=0.01)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    o = oracle.anneal(c, 40, 5, 4.0, 0.5, seed=13)
+    for algo in (BLOCKS, SLABS):
+        assert_same(run_gpu(env, t, 40, 5, 4.0, 0.5, seed=13, prec=5, algo=algo)[0], o)
+
+
+def test_mixed_family_large_instances(env):
+    """Four instances of the mixed family (N up to 160, orders 2-4, density
+    0.3, FP32) with 1024 replicas each in one graph-captured launch: every
+    reported best energy is the FP64 energy of the reported best state (checked
+    on 32 sampled replicas per instance against the oracle), and the traces
+    never rise."""
+    hobo, _ = env
+    idx = [0, 1, 2, 8]  # orders 3, 4, 2, 4
+    specs = [W.cfg_mixed_instance(0, i) for i in idx]
+    tensors = [hobo.Tensor.from_terms(s) for s in specs]
+    out = run_gpu(env, tensors, [1024] * 4, 5, 5.0, 0.01, seed=3, prec=0, mode=2)
+    rng = np.random.default_rng(2)
+    for s, g in zip(specs, out):
+        c = oracle.canonicalize(s)
+        rows = rng.choice(1024, size=32, replace=False)
+        want = oracle.energy(c, g["best_bits"][:, rows])
+        scale = oracle.active_scale(c, g["best_bits"][:, rows])
+        assert (np.abs(g["best_e"][rows] - want) <= 1e-12 * np.maximum(np.abs(want), scale)).all()
+        assert (np.diff(g["trace"]) <= 0).all()

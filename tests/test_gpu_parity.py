@@ -308,3 +308,78 @@ def test_fp16x2_accuracy_margin(env):
         errs[prec] = max(_rel_err(e, want, scale).max(), _rel_err(de.astype(np.float64), de_ref, fscale).max())
     print(f"max error / C13 floor: FP16X2 {errs[5]:.2e}, BF16X2 {errs[1]:.2e}, FP32 {errs[0]:.2e}")
     assert errs[5] <= 5e-6 and errs[5] <= 1.5 * errs[0] and errs[5] < errs[1] / 2
+
+
+def test_fp16x2_wide_dynamic_range(env):
+    """FP16X2 on coefficients spanning 2^-30 .. 2^0 in magnitude: the
+    per-tensor scale puts the largest in [2^14, 2^15), coefficients below
+    2^-17 of it lose relative precision in the lo part but keep an absolute
+    error below 2^-39 of the largest.  Energies and flip changes stay within
+    the bound that follows: sum over active terms of (2^-22 |w| + 2^-39 max|w|)
+    plus FP32 summation (1e-6 of the active absolute sum)."""
+    hobo, _ = env
+    rng = np.random.default_rng(12)
+    n = 40
+    subs, co = [], []
+    for r in (1, 2, 3):
+        s = W.lex_subsets(n, r)
+        subs.append(s)
+        mag = 2.0 ** rng.uniform(-30, 0, size=len(s))
+        co.append((mag * rng.choice([-1, 1], size=len(s))).astype(np.float32).astype(np.float64))
+    terms = W.subsets_to_terms(n, subs, co, False)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(n, 300, seed=4))
+    x = W.unpack_bits(bits, n)
+    wmax = max(abs(float(w)) for w in c.weights)
+    act_abs = np.zeros(300)
+    act_cnt = np.zeros(300)
+    for mono, w in zip(c.monos, c.weights):
+        on = x[:, list(mono)].all(axis=1)
+        act_abs += on * abs(float(w))
+        act_cnt += on
+    bound = 2.0 ** -22 * act_abs + 2.0 ** -39 * wmax * act_cnt + 1e-6 * act_abs
+    got = gpu_energy(env, t, bits, 5)
+    want = oracle.energy(c, bits)
+    assert (np.abs(got - want) <= bound).all()
+    de, _ = gpu_fields(env, t, bits, 5, want_e=False)
+    _, de_ref = oracle.fields(c, bits)
+    fs = oracle.field_scale(c, bits)
+    assert (np.abs(de.astype(np.float64) - de_ref) <= 1e-5 * np.maximum(np.abs(de_ref), fs) + 2.0 ** -39 * wmax * n * n).all()
+
+
+@pytest.mark.parametrize("prec", [5, 3])
+def test_maximum_variable_count(env, prec):
+    """N = 256, the engine's limit (four 64-bit words per state): order 2
+    (integer, INT8X4) and order 3 (real, FP16X2, sparse), energies and flip
+    changes against the oracle on ragged batches."""
+    hobo, _ = env
+    n = 256
+    if prec == 3:
+        terms = _int_instance(256, n, 2, dens=0.3, lo=-5, hi=5)
+    else:
+        rng = np.random.default_rng(256)
+        subs, co = [], []
+        for r in (1, 2, 3):
+            s = W.lex_subsets(n, r)
+            keep = rng.random(len(s)) < (0.02 if r == 3 else 0.5)
+            subs.append(s[keep])
+            co.append(rng.standard_normal(int(keep.sum())).astype(np.float32).astype(np.float64) / n)
+        terms = W.subsets_to_terms(n, subs, co, False)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    bits = W.pack_bits(W.random_states(n, 203, seed=1))
+    got = gpu_energy(env, t, bits, prec)
+    want = oracle.energy(c, bits)
+    de, e = gpu_fields(env, t, bits, prec)
+    _, de_ref = oracle.fields(c, bits)
+    if prec == 3:
+        np.testing.assert_array_equal(got, want)
+        np.testing.assert_array_equal(de, de_ref)
+        np.testing.assert_array_equal(e, want)
+    else:
+        scale = oracle.active_scale(c, bits)
+        assert _rel_err(got, want, scale).max() <= 1e-5
+        assert _rel_err(e, want, scale).max() <= 1e-5
+        fscale = oracle.field_scale(c, bits)
+        assert _rel_err(de.astype(np.float64), de_ref, fscale).max() <= 1e-5
