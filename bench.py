@@ -127,7 +127,9 @@ def main():
         t.prepare(hobo.FN_ENERGY | hobo.FN_FIELDS, sum(1 << p for p in PREC_OF.values()))
         info = eval_rates(hobo, W, torch, dev, t, B)
         info.update(int8_rates(hobo, W, torch, dev))
-        print(json.dumps({"eval_kernels": info}))
+        info.update(tt_rates(hobo, W, torch, dev))
+        info.update(gd_rates(hobo, torch, dev, t, B))
+        print(json.dumps({"eval_kernels": info, "paper_problems": paper_problems(torch)}))
         return
     t.prepare(hobo.FN_ENERGY | hobo.FN_FIELDS | hobo.FN_ANNEAL, sum(1 << p for p in PREC_OF.values()))
     W_ = (N_VARS + 63) // 64
@@ -234,6 +236,7 @@ def main():
         eval_info.update(int8_rates(hobo, W, torch, dev))
         eval_info.update(tt_rates(hobo, W, torch, dev))
         eval_info.update(gd_rates(hobo, torch, dev, t, B))
+    problems = None if args.no_eval_sweep else paper_problems(torch)
 
     multi = None
     if args.mixed_instances > 0:
@@ -277,6 +280,7 @@ def main():
         "variants": variants,
         "learned": learned_info,
         "eval_kernels": eval_info,
+        "paper_problems": problems,
         "multi_instance": multi,
         "mixed_full": mixed_full,
         "ttt_heldout": ttt,
@@ -368,6 +372,45 @@ def int8_rates(hobo, W, torch, dev, bb=8192):
         useful = (2 * sum(nnz) if fn == "energy" else 2 * sum(r * c for r, c in enumerate(nnz))) * rate / 1e12
         out[f"intenc4_{fn}_int8x4_B{bb}"] = dict(us=us, evals_per_s=rate, issued_tops=issued, dense_tops=dense,
                                                  useful_tops=useful, frac_of_peak=issued / PEAK_TFLOPS["int8x4"])
+    return out
+
+
+def paper_problems(torch, shots=10000, sweeps=300):
+    """The three worked problems of Sec. V end to end through the front-end:
+    compile (host), sample `shots` replicas on the GPU, aggregate; the time of
+    each part, the best energy and the number of distinct optimal states."""
+    import numpy as np
+
+    from paper_2407_19987_amd import frontend as F
+
+    def seating():
+        q = F.symbols_list([5, 5], "bq{}_{}")
+        wins = [[(i, j + d) for d in range(3)] for i in range(5) for j in range(3)]
+        wins += [[(i + d, j) for d in range(3)] for j in range(5) for i in range(3)]
+        return 10 * sum(q[w[0]] * q[w[1]] * q[w[2]] for w in wins) - sum(q[i, j] for i in range(5) for j in range(5))
+
+    def pythagorean():
+        q = F.symbols_list([3, 4], "bp{}_{}")
+        v = [sum((1 << k) * q[p, k] for k in range(4)) for p in range(3)]
+        return (v[0] ** 2 + v[1] ** 2 - v[2] ** 2) ** 2 + 10 * sum(np.prod(1 - q[p, :]) for p in range(3))
+
+    def tsp():
+        q = F.symbols_list([4, 2], "bt{}_{}")
+        v = [2 * q[p, 0] + q[p, 1] for p in range(3)]
+        return 10 * (v[0] * v[1] * v[2] - 6) ** 2
+
+    out = {}
+    for name, make in (("seating_5x5", seating), ("pythagorean_4bit", pythagorean), ("tsp_intenc", tsp)):
+        t0 = time.perf_counter()
+        cp = F.compile_hobo(make())
+        t1 = time.perf_counter()
+        rows = F.sample(cp, shots, sweeps=sweeps, seed=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        best = rows[0].energy
+        out[name] = dict(n_vars=cp.n_vars, order=int(cp.tensor.order), offset=cp.offset, compile_ms=(t1 - t0) * 1e3,
+                         sample_and_aggregate_ms=(t2 - t1) * 1e3, shots=shots, sweeps=sweeps, best_energy=best,
+                         optimal_states=sum(1 for r in rows if r.energy == best), distinct_states=len(rows))
     return out
 
 

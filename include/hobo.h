@@ -413,6 +413,19 @@ hobo_status hobo_proposal_features(const hobo_tensor* t, const uint64_t* x_bits,
                                    const void* de, double t_start, double t_end, int32_t sweep,
                                    int32_t schedule_sweeps, float* feats_out, float* labels_out, void* stream);
 
+/* Training transitions for the proposal network from a plain annealing run
+ * of B replicas (params: the whole schedule in `sweeps`, its temperatures,
+ * seed, precision and init; proposal METROPOLIS).  For each sweep r in
+ * `record` (host int32, increasing, within the schedule): the features of
+ * every (replica, bit) at the start of sweep r, as hobo_proposal_features
+ * gives them, into feats_out (device FP32 [n_record][B][N][3]), and the label
+ * "the bit changed during sweep r" into labels_out (device FP32
+ * [n_record][B][N]).  The chain is the one hobo_anneal_batch runs for the
+ * same arguments.  Allocates its state buffers (stream-ordered). */
+hobo_status hobo_record_transitions(hobo_tensor* t, int64_t B, const hobo_anneal_params* params,
+                                    const int32_t* record, int32_t n_record, float* feats_out, float* labels_out,
+                                    void* stream);
+
 /* ------------------------------------------------------------- autotuning */
 /* Times every launch shape of the kernels in fn_mask (1 energy: 16*rt
  * replicas x 16*ct columns per wave; 2 fields: same; 4 annealing: waves per

@@ -1098,6 +1098,68 @@ hobo_status hobo_proposal_features(const hobo_tensor* tc, const uint64_t* x_bits
   return ok();
 }
 
+hobo_status hobo_record_transitions(hobo_tensor* t, int64_t B, const hobo_anneal_params* params,
+                                    const int32_t* record, int32_t n_record, float* feats_out, float* labels_out,
+                                    void* stream) {
+  g_err.clear();
+  if (!t || !params || !feats_out || !labels_out || (n_record > 0 && !record))
+    return fail(HOBO_ERR_INVALID_ARG, "NULL argument");
+  if (B < 1 || B > ((int64_t)1 << 31)) return fail(HOBO_ERR_INVALID_ARG, "B out of range");
+  const hobo_anneal_params P = *params;
+  if (P.sweeps < 1) return fail(HOBO_ERR_INVALID_ARG, "the schedule needs at least one sweep");
+  if (P.proposal != HOBO_PROPOSAL_METROPOLIS) return fail(HOBO_ERR_INVALID_ARG, "transitions come from plain runs");
+  for (int32_t k = 0; k < n_record; ++k)
+    if (record[k] < 0 || record[k] >= P.sweeps || (k > 0 && record[k] <= record[k - 1]))
+      return fail(HOBO_ERR_INVALID_ARG, "record must list increasing sweeps of the schedule");
+  if (hobo_status s = need_device()) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = t->t.n_vars, W = (n + 63) / 64;
+  const size_t xb = (size_t)W * (size_t)B * 8, deb = (size_t)B * (size_t)n * (t->t.integer ? 8 : 4);
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  void* work = nullptr;
+  if (hobo_status s = hip_status(hipMallocAsync(&work, align(xb) * 3 + align((size_t)B * 8) + align(deb), st),
+                                 "hipMallocAsync"))
+    return s;
+  char* w = static_cast<char*>(work);
+  uint64_t* x = reinterpret_cast<uint64_t*>(w);
+  uint64_t* bx = reinterpret_cast<uint64_t*>(w + align(xb));
+  uint64_t* xprev = reinterpret_cast<uint64_t*>(w + 2 * align(xb));
+  void* be = w + 3 * align(xb);
+  void* de = w + 3 * align(xb) + align((size_t)B * 8);
+  hobo_anneal_params q = P;
+  q.schedule_sweeps = P.sweeps;
+  q.attempt = nullptr;
+  hobo_tensor* ts[1] = {t};
+  const int64_t reps[1] = {B};
+  hobo_status rc = HOBO_OK;
+  auto anneal = [&](int first, int count, int init, int cont) {
+    q.first_sweep = first;
+    q.sweeps = count;
+    q.init = init;
+    q.continue_best = cont;
+    if (rc == HOBO_OK) rc = hobo_anneal_batch(ts, 1, reps, &q, x, bx, be, nullptr, HOBO_LAUNCH_PERSISTENT, stream);
+  };
+  // the start states (no sweep), then the schedule in calls that end before
+  // each recorded sweep, which runs alone between its features and its labels
+  anneal(0, 0, P.init, 0);
+  int s = 0;
+  const int fprec = P.precision == HOBO_PREC_INT8X4 ? HOBO_PREC_INT8X4 : P.precision;
+  for (int32_t k = 0; k < n_record && rc == HOBO_OK; ++k) {
+    const int r = record[k];
+    if (r > s) anneal(s, r - s, HOBO_INIT_GIVEN, 1);
+    if (rc == HOBO_OK) rc = hobo_local_fields(t, x, B, fprec, de, nullptr, stream);
+    if (rc == HOBO_OK) rc = hip_status(hipMemcpyAsync(xprev, x, xb, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    anneal(r, 1, HOBO_INIT_GIVEN, 1);
+    if (rc == HOBO_OK)
+      rc = hobo_proposal_features(t, xprev, x, B, de, P.t_start, P.t_end, r, P.sweeps,
+                                  feats_out + (size_t)k * (size_t)B * (size_t)n * 3,
+                                  labels_out + (size_t)k * (size_t)B * (size_t)n, stream);
+    s = r + 1;
+  }
+  (void)hipFreeAsync(work, st);
+  return rc == HOBO_OK ? ok() : rc;
+}
+
 // ------------------------------------------------------------ gradient descent
 hobo_status hobo_gd_gradient(const hobo_tensor* tc, const double* p, int64_t B, double* g_out, void* stream) {
   g_err.clear();

@@ -41,7 +41,7 @@ EXPORTS = [
     "hobo_mlp_forward", "hobo_mlp_grad", "hobo_mlp_train", "hobo_proposal_features", "hobo_autotune",
     "hobo_tensor_layout_info", "hobo_energy_noalloc", "hobo_aggregate",
     "hobo_tt_build", "hobo_tt_free", "hobo_tt_info", "hobo_tt_cores", "hobo_tt_energy",
-    "hobo_gd_gradient", "hobo_gd_batch",
+    "hobo_gd_gradient", "hobo_gd_batch", "hobo_record_transitions",
 ]
 
 
@@ -103,6 +103,7 @@ def _load():
     lib.hobo_tt_cores.argtypes = [P, P, i64]
     lib.hobo_tt_energy.argtypes = [P, P, i64, P, P]
     lib.hobo_gd_gradient.argtypes = [P, P, i64, P, P]
+    lib.hobo_record_transitions.argtypes = [P, i64, ctypes.POINTER(AnnealParams), P, i32, P, P, P]
     lib.hobo_gd_batch.argtypes = [P, i64, ctypes.POINTER(GDParams), P, P, P, P]
     lib.hobo_local_fields.argtypes = [P, P, i64, i32, P, P, P]
     lib.hobo_anneal_batch.argtypes = [P, i32, P, ctypes.POINTER(AnnealParams), P, P, P, P, i32, P]
@@ -477,3 +478,20 @@ def gd_batch(t: Tensor, B: int, p_inout, x_out, e_out, *, iterations: int, eta: 
     prm = GDParams(int(iterations), int(init), float(eta), int(seed))
     _check(lib.hobo_gd_batch(t.handle, int(B), ctypes.byref(prm), _dev_ptr(p_inout), _dev_ptr(x_out),
                              _dev_ptr(e_out), _stream(stream)))
+
+
+def record_transitions(t: Tensor, B: int, record, feats_out, labels_out, *, sweeps: int, t_start: float, t_end: float,
+                       seed: int, precision: int = PREC_FP32, init: int = INIT_RANDOM, stream=None):
+    """hobo_record_transitions: features before and labels of the sweeps in
+    `record` of a plain run; feats_out [len(record)][B][N][3], labels_out
+    [len(record)][B][N] device FP32."""
+    rec = np.ascontiguousarray(sorted(set(int(r) for r in record)), dtype=np.int32)
+    n = t.n_vars
+    if feats_out.numel() < len(rec) * B * n * 3 or labels_out.numel() < len(rec) * B * n:
+        raise ValueError("feats_out / labels_out too small")
+    p = AnnealParams()
+    p.sweeps, p.precision, p.t_start, p.t_end, p.seed = int(sweeps), int(precision), float(t_start), float(t_end), \
+        int(seed)
+    p.init, p.proposal = int(init), PROPOSAL_METROPOLIS
+    _check(lib.hobo_record_transitions(t.handle, int(B), ctypes.byref(p), _np_ptr(rec), len(rec),
+                                       _dev_ptr(feats_out), _dev_ptr(labels_out), _stream(stream)))

@@ -2,10 +2,10 @@
 driven entirely through the C-ABI (every computation runs in the library's
 kernels; this module only orders the calls and holds device buffers).
 
-* :func:`record_transitions` runs a plain annealing schedule one sweep per
-  call.  Before each recorded sweep the fields of the current states give
-  every bit's features [x_i, beta_s dE_i, beta_s ||H_i||]; after the sweep its
-  label is whether the bit changed.
+* :func:`record_transitions` (hobo_record_transitions) runs a plain
+  annealing schedule; before each recorded sweep the fields of the current
+  states give every bit's features [x_i, beta_s dE_i, beta_s ||H_i||]; after
+  the sweep its label is whether the bit changed.
 * :func:`train` fits the 3 -> 256 -> 1 network on those transitions
   (hobo_mlp_train: BCE, Adam, deterministic sums).
 * :func:`anneal_timed` runs one annealing call (plain or LEARNED) and returns
@@ -20,37 +20,19 @@ from . import hobo
 
 def record_transitions(t: "hobo.Tensor", replicas: int, sweeps: int, t_start: float, t_end: float, seed: int,
                        record: list, precision: int = hobo.PREC_BF16X2):
-    """Transitions of a plain annealing run: for each sweep index in
-    ``record``, the features of every (replica, bit) at the sweep's start and
-    the label "the bit changed during the sweep".  Returns device tensors
-    (feats [M][3], labels [M]) with M = len(record) * replicas * N."""
+    """Transitions of a plain annealing run (hobo_record_transitions): for
+    each sweep index in ``record``, the features of every (replica, bit) at
+    the sweep's start and the label "the bit changed during the sweep".
+    Returns device tensors (feats [M][3], labels [M]) with
+    M = len(record) * replicas * N."""
     import torch
 
     n, b = t.n_vars, int(replicas)
-    w = (n + 63) // 64
-    dev = torch.device("cuda")
-    x = torch.zeros(w * b, dtype=torch.int64, device=dev)
-    bx = torch.zeros_like(x)
-    be = torch.zeros(b, dtype=torch.int64 if t.integer else torch.float64, device=dev)
-    de = torch.empty((b, n), dtype=torch.int64 if t.integer else torch.float32, device=dev)
     rec = sorted(set(int(s) for s in record if 0 <= int(s) < sweeps))
-    feats = torch.empty((len(rec), b, n, 3), dtype=torch.float32, device=dev)
-    labels = torch.empty((len(rec), b, n), dtype=torch.float32, device=dev)
-    common = dict(t_start=t_start, t_end=t_end, seed=seed, precision=precision, schedule_sweeps=sweeps)
-    # the random start states (no sweep), then one call per sweep of the schedule
-    hobo.anneal_batch(t, b, x, bx, be, sweeps=0, init=hobo.INIT_RANDOM, first_sweep=0, **common)
-    s = 0
-    for k, r in enumerate(rec):
-        if r > s:  # the sweeps before the recorded one, in one call
-            hobo.anneal_batch(t, b, x, bx, be, sweeps=r - s, init=hobo.INIT_GIVEN, first_sweep=s, continue_best=True,
-                              **common)
-        hobo.local_fields(t, x, b, precision, de)
-        x_before = x.clone()
-        hobo.anneal_batch(t, b, x, bx, be, sweeps=1, init=hobo.INIT_GIVEN, first_sweep=r, continue_best=True,
-                          **common)
-        hobo.proposal_features(t, x_before, b, de, feats[k], t_start=t_start, t_end=t_end, sweep=r,
-                               schedule_sweeps=sweeps, x_after=x, labels_out=labels[k])
-        s = r + 1
+    feats = torch.empty((len(rec), b, n, 3), dtype=torch.float32, device="cuda")
+    labels = torch.empty((len(rec), b, n), dtype=torch.float32, device="cuda")
+    hobo.record_transitions(t, b, rec, feats, labels, sweeps=sweeps, t_start=t_start, t_end=t_end, seed=seed,
+                            precision=precision)
     return feats.reshape(-1, 3).contiguous(), labels.reshape(-1).contiguous()
 
 

@@ -135,3 +135,33 @@ def test_features_and_labels(env, integer):
     else:
         sc = beta * oracle.field_scale(c, W.pack_bits(x))
         assert (np.abs(got[..., 1] - want[..., 1]) <= 1e-5 * np.maximum(np.abs(want[..., 1]), sc)).all()
+
+
+def test_record_transitions_match_oracle_chain(env):
+    """hobo_record_transitions on an integer instance: for each recorded sweep
+    the features equal the oracle's features of the oracle chain's states at
+    the start of that sweep (with that sweep's beta), and the labels its
+    flips during the sweep."""
+    hobo, torch = env
+    terms = W.cfg_int3(seed=9, n=24)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    n, B, S, T0, T1, seed = c.n_vars, 40, 12, 4.0, 0.3, 21
+    rec = [0, 3, 7, 11]
+    feats = torch.empty((len(rec), B, n, 3), dtype=torch.float32, device="cuda")
+    labels = torch.empty((len(rec), B, n), dtype=torch.float32, device="cuda")
+    hobo.record_transitions(t, B, rec, feats, labels, sweeps=S, t_start=T0, t_end=T1, seed=seed,
+                            precision=hobo.PREC_FP32)
+    torch.cuda.synchronize()
+    temps = oracle.schedule(T0, T1, S)
+    x = oracle.anneal(c, B, 0, T0, T1, seed=seed)["final_bits"]  # the random start states
+    s = 0
+    for k, r in enumerate(rec):
+        if r > s:
+            x = oracle.anneal(c, B, r - s, T0, T1, seed=seed, init_bits=x, first_sweep=s, schedule_sweeps=S)["final_bits"]
+        after = oracle.anneal(c, B, 1, T0, T1, seed=seed, init_bits=x, first_sweep=r, schedule_sweeps=S)["final_bits"]
+        want = M.features(c, x, 1.0 / temps[r])
+        np.testing.assert_array_equal(feats[k].cpu().numpy(), want.astype(np.float32))
+        np.testing.assert_array_equal(labels[k].cpu().numpy(),
+                                      (W.unpack_bits(x, n) != W.unpack_bits(after, n)).astype(np.float32))
+        x, s = after, r + 1
