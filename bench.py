@@ -256,6 +256,7 @@ def main():
         cpu = cpu_baseline(terms, S)
 
     traffic = read_traffic(args.precision, B, S, main_res["anneal_launches"])
+    l2 = read_l2_stream(args.precision, B, S, main_res["anneal_launches"], main_res["anneal_ms"])
     rec = {
         "metric": "HOBO energy+ΔE evals/s; time-to-target energy, plain vs split/learned",
         "value": value,
@@ -276,7 +277,8 @@ def main():
                      "traffic": traffic, "kernel": "anneal_block_kernel",
                      "flops_per_launch": flops // max(main_res["anneal_launches"], 1),
                      "avg_launch_ms": main_res["anneal_ms"] / max(main_res["anneal_launches"], 1),
-                     "launches_per_step": main_res["anneal_launches"]},
+                     "launches_per_step": main_res["anneal_launches"],
+                     "measured_bound": l2},
         "variants": variants,
         "learned": learned_info,
         "eval_kernels": eval_info,
@@ -626,6 +628,28 @@ def cpu_baseline(terms, S):
             "sample": f"oracle annealer, {nrep} replicas x the first {nsw} sweeps of the same N=128 order-3 "
                       f"instance's {S}-sweep schedule (T {T0}->{T1}), {dt:.1f} s on {all_threads} threads of "
                       f"{model}; single core: 16 replicas x 4 sweeps, {dt1:.1f} s"}
+
+
+def read_l2_stream(precision, B, S, launches, anneal_ms):
+    """The annealer's measured bound: the L2 -> compute-unit stream of
+    coefficient tiles.  L1 -> L2 read requests (128 B) per launch from the
+    committed counter summary (measured on the BF16X2 form, whose tiles have
+    the size of the FP16X2 ones), over this run's launch time, against the L2
+    request peak (16 requests of 128 B per clock per XCD, 8 XCDs, 2.4 GHz)."""
+    try:
+        import re
+
+        txt = open(os.path.join(ROOT, "profiles", "anneal_block_l2_order3_n128_b4096.md")).read()
+        req = float(re.search(r"`TCP_TCC_READ_REQ_sum`[^|]*\| ([0-9,]+)", txt).group(1).replace(",", ""))
+        if precision not in ("bf16x2", "fp16x2") or B != REPLICAS or S != SWEEPS or launches != 4:
+            return None
+        tbps = req * 128 / (anneal_ms / launches * 1e-3) / 1e12
+        peak = 16 * 128 * 8 * 2.4e9 / 1e12
+        return {"resource": "L2 -> CU stream of coefficient tiles", "achieved": tbps, "peak": peak, "unit": "TB/s",
+                "frac": tbps / peak, "requests_per_launch": req,
+                "source": "profiles/anneal_block_l2_order3_n128_b4096.md"}
+    except (OSError, AttributeError, ValueError):
+        return None
 
 
 def read_traffic(precision, B, S, launches):
