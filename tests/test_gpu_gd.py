@@ -27,14 +27,15 @@ def _inst(seed, n, k, integer, dens=0.6):
     subs, co = [], []
     for r in range(1, k + 1):
         s = W.lex_subsets(n, r)
-        keep = rng.random(len(s)) < dens
+        keep = rng.random(len(s)) < (dens if n < 200 else 0.1)
         subs.append(s[keep])
         co.append(rng.integers(-6, 7, size=int(keep.sum())) if integer else
                   rng.standard_normal(int(keep.sum())).astype(np.float32).astype(np.float64))
     return W.subsets_to_terms(n, subs, co, integer)
 
 
-CASES = [(1, 7, 3, False), (2, 37, 3, True), (3, 20, 4, False), (4, 130, 2, False), (5, 70, 3, False)]
+CASES = [(1, 7, 3, False), (2, 37, 3, True), (3, 20, 4, False), (4, 130, 2, False), (5, 70, 3, False),
+         (6, 256, 2, False), (7, 14, 6, True)]
 
 
 def _abs_scale(c, p):

@@ -29,7 +29,8 @@ def _instances():
     del rng
     return [("tsp", W.paper_tsp_intenc), ("pyth", W.paper_pythagorean), ("int3_n9", lambda: rand(1, 9, 3, True)),
             ("real4_n6", lambda: rand(2, 6, 4, False)), ("real3_n16", lambda: rand(3, 16, 3, False, 0.5)),
-            ("int2_n24", lambda: rand(4, 24, 2, True, 0.3))]
+            ("int2_n24", lambda: rand(4, 24, 2, True, 0.3)), ("int7_n5", lambda: rand(5, 5, 5, True, 0.7)),
+            ("real5_n7", lambda: rand(6, 7, 5, False, 0.4))]
 
 
 @pytest.mark.parametrize("name,make", _instances())
