@@ -256,7 +256,7 @@ def main():
         cpu = cpu_baseline(terms, S)
 
     traffic = read_traffic(args.precision, B, S, main_res["anneal_launches"])
-    l2 = read_l2_stream(args.precision, B, S, main_res["anneal_launches"], main_res["anneal_ms"])
+    cu_path = read_cu_path(args.precision, B, S, main_res["anneal_launches"], main_res["anneal_ms"])
     rec = {
         "metric": "HOBO energy+ΔE evals/s; time-to-target energy, plain vs split/learned",
         "value": value,
@@ -278,7 +278,7 @@ def main():
                      "flops_per_launch": flops // max(main_res["anneal_launches"], 1),
                      "avg_launch_ms": main_res["anneal_ms"] / max(main_res["anneal_launches"], 1),
                      "launches_per_step": main_res["anneal_launches"],
-                     "measured_bound": l2},
+                     "measured_bound": cu_path},
         "variants": variants,
         "learned": learned_info,
         "eval_kernels": eval_info,
@@ -630,24 +630,33 @@ def cpu_baseline(terms, S):
                       f"{model}; single core: 16 replicas x 4 sweeps, {dt1:.1f} s"}
 
 
-def read_l2_stream(precision, B, S, launches, anneal_ms):
-    """The annealer's measured bound: the L2 -> compute-unit stream of
-    coefficient tiles.  L1 -> L2 read requests (128 B) per launch from the
-    committed counter summary (measured on the BF16X2 form, whose tiles have
-    the size of the FP16X2 ones), over this run's launch time, against the L2
-    request peak (16 requests of 128 B per clock per XCD, 8 XCDs, 2.4 GHz)."""
+def read_cu_path(precision, B, S, launches, anneal_ms):
+    """The annealer's measured bound: each compute unit's vector-memory
+    return path, which carries the coefficient tiles into registers.  The
+    L1 -> L2 read requests (128 B) per launch and the data-return unit's busy
+    share come from the committed counter summary of the same kernel source;
+    the bytes are taken over this run's launch time, against 64 B per clock
+    per CU (256 CUs, 2.4 GHz)."""
     try:
+        import hashlib
         import re
 
-        txt = open(os.path.join(ROOT, "profiles", "anneal_block_l2_order3_n128_b4096.md")).read()
-        req = float(re.search(r"`TCP_TCC_READ_REQ_sum`[^|]*\| ([0-9,]+)", txt).group(1).replace(",", ""))
-        if precision not in ("bf16x2", "fp16x2") or B != REPLICAS or S != SWEEPS or launches != 4:
+        prof = os.path.join(ROOT, "profiles", "anneal_block_cu_path_order3_n128_fp16x2.md")
+        src = os.path.join(ROOT, "paper_2407_19987_amd", "csrc", "anneal_block.hip")
+        txt = open(prof).read()
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() not in txt:
+            return None
+        req = float(re.search(r"`TCP_TCC_READ_REQ_sum`[^|]*\| ([0-9.e+]+) \|", txt).group(1))
+        busy = float(re.search(r"\| data return \(TD\) busy \| ([0-9.]+) %", txt).group(1)) / 100
+        wait = float(re.search(r"stalled waiting for the L1[^|]*\| ([0-9.]+) %", txt).group(1)) / 100
+        if precision != "fp16x2" or B != REPLICAS or S != SWEEPS or launches != 4:
             return None
         tbps = req * 128 / (anneal_ms / launches * 1e-3) / 1e12
-        peak = 16 * 128 * 8 * 2.4e9 / 1e12
-        return {"resource": "L2 -> CU stream of coefficient tiles", "achieved": tbps, "peak": peak, "unit": "TB/s",
-                "frac": tbps / peak, "requests_per_launch": req,
-                "source": "profiles/anneal_block_l2_order3_n128_b4096.md"}
+        peak = 64 * 256 * 2.4e9 / 1e12
+        return {"resource": "per-CU vector-memory return path (coefficient tiles into registers)",
+                "achieved": tbps, "peak": peak, "unit": "TB/s", "frac": tbps / peak,
+                "l1_fill_requests_per_launch": req, "data_return_busy": busy, "data_return_waiting_on_l1": wait,
+                "source": "profiles/anneal_block_cu_path_order3_n128_fp16x2.md"}
     except (OSError, AttributeError, ValueError):
         return None
 
