@@ -630,21 +630,35 @@ def cpu_baseline(terms, S):
                       f"{model}; single core: 16 replicas x 4 sweeps, {dt1:.1f} s"}
 
 
+# what the blocked annealer streams is set by its kernel, the layout packer
+# and the work schedule: a counter summary holds for these sources only
+ANNEALER_SOURCES = ("anneal_block.hip", "pack.cpp", "schedule.cpp")
+
+
+def annealer_digest() -> str:
+    """sha256 over the blocked annealer's sources, in ANNEALER_SOURCES order."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ANNEALER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_19987_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def read_cu_path(precision, B, S, launches, anneal_ms):
     """The annealer's measured bound: each compute unit's vector-memory
     return path, which carries the coefficient tiles into registers.  The
     L1 -> L2 read requests (128 B) per launch and the data-return unit's busy
-    share come from the committed counter summary of the same kernel source;
+    share come from the committed counter summary of the same annealer sources;
     the bytes are taken over this run's launch time, against 64 B per clock
     per CU (256 CUs, 2.4 GHz)."""
     try:
-        import hashlib
         import re
 
         prof = os.path.join(ROOT, "profiles", "anneal_block_cu_path_order3_n128_fp16x2.md")
-        src = os.path.join(ROOT, "paper_2407_19987_amd", "csrc", "anneal_block.hip")
         txt = open(prof).read()
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() not in txt:
+        if annealer_digest() not in txt:
             return None
         req = float(re.search(r"`TCP_TCC_READ_REQ_sum`[^|]*\| ([0-9.e+]+) \|", txt).group(1))
         busy = float(re.search(r"\| data return \(TD\) busy \| ([0-9.]+) %", txt).group(1)) / 100
@@ -663,15 +677,13 @@ def read_cu_path(precision, B, S, launches, anneal_ms):
 
 def read_traffic(precision, B, S, launches):
     """HBM traffic of the dominant kernel from the committed counter summary,
-    valid only for the kernel source and precision it was measured on."""
+    valid only for the annealer sources and precision it was measured on."""
     try:
-        import hashlib
         import re
 
-        src = os.path.join(ROOT, "paper_2407_19987_amd", "csrc", "anneal_block.hip")
         prof = os.path.join(ROOT, "profiles", f"anneal_block_traffic_order3_n128_b4096_{precision}.md")
         txt = open(prof).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        digest = annealer_digest()
         row = re.search(r"`anneal_block_kernel<%d, \d+>` \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|" % PREC_OF[precision],
                         txt)
         fs = float(re.search(r"FETCH x ([0-9.]+)", txt).group(1))

@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.
 # (values of the Prec enum) so that its many shapes compile in parallel, and
 # so are both annealers
 SOURCES = [("anneal_kernels.hip", "", []), ("anneal_block.hip", "", []), ("mlp_kernels.hip", "", []),
-           ("eval_kernels.hip", "", []), ("timing.hip", "", []), ("pack.cpp", "", []), ("canon.cpp", "", []), ("results.cpp", "", []), ("tt.cpp", "", []), ("tt_kernels.hip", "", []), ("gd.cpp", "", []),
+           ("eval_kernels.hip", "", []), ("timing.hip", "", []), ("pack.cpp", "", []), ("canon.cpp", "", []), ("results.cpp", "", []), ("tt.cpp", "", []), ("tt_kernels.hip", "", []), ("gd.cpp", "", []), ("schedule.cpp", "", []),
            ("gd_kernels.hip", "", []),
            ("abi.cpp", "", [])] + [
     ("eval_prec.hip", f"p{p}", [f"-DHOBO_EVAL_PREC={p}"]) for p in (0, 1, 2, 3, 5)] + [

@@ -4,9 +4,15 @@
 // A sweep visits the variables in order, 16 at a time.  For a block J of 16
 // consecutive variables and the state x0 at the block's start, the matrix
 // cores compute for 16 replicas
-//   g_a(x0)       = sum_{S containing a} w_S prod_{S minus a} x0       (a in J)
 //   H_ab(x0)      = sum_{S containing a, b} w_S prod_{S minus a, b} x0  (a < b in J)
-// and the block's order-3 coefficients w_abc (a, b, c in J) come from a
+//   F_a(x0)       = sum of w_S prod_{S minus a} x0 over the S containing a
+//                   and no other variable of J, minus the same over the S
+//                   containing a and two others of J                    (a in J)
+// and the decision wave completes the fields as
+//   g_a(x0)       = F_a(x0) + sum_{b in J, b != a} x0_b H_ab(x0)
+// (the terms with one other variable b of J are in x0_b H_ab once, those
+// with two are there twice), so the field list carries about a fifth fewer
+// rows.  The block's order-3 coefficients w_abc (a, b, c in J) come from a
 // table.  Because the energy is multilinear, the field of bit a after the
 // flips of earlier bits c of the block (x_c -> x_c + d_c, d_c in {-1, 0, 1})
 // is exactly
@@ -130,8 +136,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
   // (two buffers: a block's early chunks run while the decisions of the one
   // before it still read its fields)
   __shared__ __attribute__((aligned(16))) float sG[2][NS][16][16];
-  // pair couplings [rep][a][b], b < a; replicas 260 floats apart (no bank
-  // conflicts when the decision wave reads its rows as float4)
+  // pair couplings [rep][a][b], stored at both (a, b) and (b, a); replicas
+  // 260 floats apart (no bank conflicts when the decision wave reads its
+  // rows as float4)
   constexpr int kHRep = 260;
   __shared__ __attribute__((aligned(16))) float sH[16 * kHRep];
   __shared__ unsigned short sPC[128];  // pair column -> (a << 8) | b (unused columns -> 0)
@@ -321,6 +328,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
 #pragma unroll
           for (int ww = 0; ww < NS; ++ww) reinterpret_cast<f4*>(&sG[gb][ww][0][0])[lane] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        unsigned char* myb = reinterpret_cast<unsigned char*>(sbits) + rep * 32 + 2 * q;
+        unsigned xb = (unsigned)myb[0] | ((unsigned)myb[1] << 8);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int a = sub + 4 * i;
@@ -333,10 +342,42 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
             }
           }
         }
+        // The field list leaves out the terms with exactly one other bit b of
+        // the block and holds the block's triples negated: adding
+        // sum_b x0_b H_ab(x0) completes g_a(x0).  Row a of H (stored at both
+        // (a, b) and (b, a)) is read as four float4, two rows at a time (a
+        // loop of two steps, with the lane layout read again, keeps the
+        // decision chain's registers free).
+        {
+          const int ln = lane_id();
+          const int rp = ln >> 2, sb = ln & 3;
+          const unsigned char* xr = reinterpret_cast<const unsigned char*>(sbits) + rp * 32 + 2 * q;
+          const unsigned x0 = (unsigned)xr[0] | ((unsigned)xr[1] << 8);
+#pragma unroll 1
+          for (int i2 = 0; i2 < 4; i2 += 2) {
+            float corr[2] = {0.0f, 0.0f};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int a = sb + 4 * (i2 + h);
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const f4 v = *reinterpret_cast<const f4*>(&sH[rp * kHRep + a * 16 + 4 * k]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  corr[h] += (4 * k + e != a && ((x0 >> (4 * k + e)) & 1u)) ? v[e] : 0.0f;
+              }
+            }
+            if (i2 == 0) {
+              gq[0] += corr[0];
+              gq[1] += corr[1];
+            } else {
+              gq[2] += corr[0];
+              gq[3] += corr[1];
+            }
+          }
+        }
         for (int e = lane; e < 16 * kHRep / 4; e += 64)
           reinterpret_cast<f4*>(&sH[0])[e] = f4{0.f, 0.f, 0.f, 0.f};
-        unsigned char* myb = reinterpret_cast<unsigned char*>(sbits) + rep * 32 + 2 * q;
-        unsigned xb = (unsigned)myb[0] | ((unsigned)myb[1] << 8);
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           if (!((amask >> c) & 1u)) continue;  // not attempted (or past the last variable)
@@ -543,8 +584,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 8
             } else {
               const unsigned ab = sPC[16 * (sl.tgt - 1) + j];
               float* dst = &sH[4 * g * kHRep + (ab >> 8) * 16 + (ab & 0xFFu)];
+              float* dsu = &sH[4 * g * kHRep + (ab & 0xFFu) * 16 + (ab >> 8)];  // the symmetric entry
 #pragma unroll
-              for (int r = 0; r < 4; ++r) dst[kHRep * r] = acc.v[r];
+              for (int r = 0; r < 4; ++r) {
+                dst[kHRep * r] = acc.v[r];
+                dsu[kHRep * r] = acc.v[r];
+              }
             }
             acc_zero<P>(acc);
           }

@@ -70,7 +70,9 @@ struct SlabMeta {     // annealer: per-variable slab of the local field
 
 // Blocked annealer: variables in blocks of 16.  For block q (variables
 // J = 16q .. 16q+15) list 0 is the field matrix of the block's 16 columns
-// (rows: monomials of order <= k-1), lists 1..8 are the pair matrices of the
+// (rows: monomials of order <= k-1 with no variable of J, and the pairs
+// inside J with the entry negated; the kernel adds sum_b x_b H_ab for the
+// rest), lists 1..8 are the pair matrices of the
 // 120 pairs (a, b) of J, 16 pairs per list (rows: monomials of order <= k-2,
 // entry w_{row u {a, b}}), and the block's 16x16x16 table holds the order-3
 // coefficients w_{abc} of triples inside J.  Every chunk of these lists has
@@ -258,6 +260,10 @@ int check_prec(const Tensor* t, int prec, std::string* err);
 int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err);
 // the blocked annealer's schedule for nw-wave work-groups (built on first use)
 int get_block_schedule(Tensor* t, Packed* pk, int nw, bool masked, const BlockSchedule** out, std::string* err);
+// the schedule's slot words and per-(block, wave) headers for NS streaming
+// waves (host only; get_block_schedule uploads them)
+void build_block_schedule(const std::vector<BlockMeta>& blocks, int ns, bool masked, std::vector<uint32_t>* words,
+                          std::vector<uint32_t>* hdr);
 int get_terms(Tensor* t, TermsDev** out, std::string* err);
 int get_row_norms(Tensor* t, const double** out, std::string* err);
 

@@ -452,12 +452,20 @@ int get_packed(Tensor* t, int mode, int prec, Packed** out, std::string* err) {
         int in[kMaxOrder], nin = 0;  // positions of s inside the block
         for (int a = 0; a < len; ++a)
           if (s[a] >= j0 && s[a] < j0 + kBlockBits) in[nin++] = a;
-        for (int u = 0; u < nin; ++u) {  // field of variable s[in[u]]: row S minus it
-          int nr = 0;
-          for (int b = 0; b < len; ++b)
-            if (b != in[u]) rest[nr++] = s[b];
-          scatter(rg, rest, nr, s[in[u]] - j0, wf, wi);
-        }
+        // field of variable s[in[u]]: row S minus it.  A row with exactly one
+        // other variable b of the block is left out: the kernel adds
+        // sum_b x_b H_ab(x0), which holds those terms, and counts every row
+        // with two (a triple inside the block) twice, so that row is stored
+        // with its sign reversed.  Rows with no variable of the block are
+        // stored as they are.
+        if (nin == 1 || nin == 3)
+          for (int u = 0; u < nin; ++u) {
+            int nr = 0;
+            for (int b = 0; b < len; ++b)
+              if (b != in[u]) rest[nr++] = s[b];
+            const double sg = nin == 3 ? -1.0 : 1.0;
+            scatter(rg, rest, nr, s[in[u]] - j0, sg * wf, nin == 3 ? -wi : wi);
+          }
         for (int u = 0; u < nin; ++u)
           for (int v = u + 1; v < nin; ++v) {  // coupling of the pair: row S minus both
             int nr = 0;
@@ -603,57 +611,8 @@ int get_block_schedule(Tensor* t, Packed* pk, int nw, bool masked, const BlockSc
     *err = "blocked schedule: more chunks than a slot word holds";
     return HOBO_ERR_RANGE;
   }
-  constexpr int D = kBlockRing;
   std::vector<uint32_t> words, hdr;
-  auto pad_to_round = [&](size_t from) {
-    while ((words.size() - from) % D) words.push_back(kSlotPad);
-  };
-  for (const BlockMeta& m : pk->h_blocks) {
-    // early part: the leading `nearly` field chunks in equal contiguous
-    // ranges; late part: a quota Q of late field chunks plus pair chunks per
-    // wave (pair tile t belongs to wave t mod NS), the late field chunks in
-    // order, the last wave taking whatever remains
-    const int ne = masked ? 0 : (int)m.nearly;
-    const int nl = (int)m.nchunks[0] - ne;
-    const int npt = (int)m.npt;
-    auto pairs_of = [&](int v) {
-      int c = 0;
-      for (int tt = v; tt < npt; tt += ns) c += (int)m.nchunks[1 + tt];
-      return c;
-    };
-    int tot = nl;
-    for (int tt = 0; tt < npt; ++tt) tot += (int)m.nchunks[1 + tt];
-    const int quota = (tot + ns - 1) / ns;
-    int loff = 0;
-    for (int v = 0; v < ns; ++v) {
-      const int e0 = ne * v / ns, e1 = ne * (v + 1) / ns;
-      int lc = std::max(0, quota - pairs_of(v));
-      lc = v == ns - 1 ? nl - loff : std::min(lc, nl - loff);
-      const uint32_t c0 = m.chunk0[0];
-      // the wave's last field chunk closes its field list
-      const int64_t last = lc > 0 ? (int64_t)c0 + ne + loff + lc - 1 : (e1 > e0 ? (int64_t)c0 + e1 - 1 : -1);
-      auto chunk_word = [&](uint32_t c, bool close, int tgt) {
-        return (c + 1u) | ((close ? 1u : 0u) << 20) | ((uint32_t)tgt << 22);
-      };
-      const size_t base = words.size();
-      for (int c = e0; c < e1; ++c) words.push_back(chunk_word(c0 + c, (int64_t)(c0 + c) == last, 0));
-      pad_to_round(base);
-      const int pe = (int)(words.size() - base);
-      for (int c = 0; c < lc; ++c) {
-        const uint32_t cc = c0 + (uint32_t)(ne + loff + c);
-        words.push_back(chunk_word(cc, (int64_t)cc == last, 0));
-      }
-      for (int tt = v; tt < npt; tt += ns)
-        for (uint32_t c = 0; c < m.nchunks[1 + tt]; ++c)
-          words.push_back(chunk_word(m.chunk0[1 + tt] + c, c + 1 == m.nchunks[1 + tt], 1 + tt));
-      pad_to_round(base);
-      if (words.size() == base)
-        for (int d = 0; d < D; ++d) words.push_back(kSlotPad);
-      hdr.push_back((uint32_t)base);
-      hdr.push_back(((uint32_t)pe << 16) | (uint32_t)(words.size() - base));
-      loff += lc;
-    }
-  }
+  build_block_schedule(pk->h_blocks, ns, masked, &words, &hdr);
   for (uint32_t w : words)
     if ((w & 0xFFFFFu) >= (uint32_t)pk->ntiles) {
       *err = "blocked schedule: tile index out of range";

@@ -1,8 +1,9 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU
 only): the oracle's C code, and the library's host-side canonicaliser,
-result aggregation and tensor-train decomposition, each driven over seeded
-random inputs by a small driver (tests/sanitize/); any sanitizer report or a
-non-zero exit fails the test.  Built with gcc / g++, no device code."""
+result aggregation, tensor-train decomposition and blocked-annealer work
+schedule, each driven over seeded random inputs by a small driver
+(tests/sanitize/); any sanitizer report, failed check or non-zero exit fails
+the test.  Built with gcc / g++, no device code."""
 import os
 import shutil
 import subprocess
@@ -37,5 +38,15 @@ def test_library_host_code_under_sanitizers(tmp_path):
     _run(["g++", "-std=c++17", *SAN, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", csrc,
           os.path.join(csrc, "canon.cpp"), os.path.join(csrc, "results.cpp"), os.path.join(csrc, "tt.cpp"),
           os.path.join(HERE, "sanitize", "host_driver.cpp"), "-o", exe], tmp_path)
+    r = subprocess.run([exe], capture_output=True, text=True, env=ENV)
+    assert r.returncode == 0 and "ERROR" not in r.stderr and "runtime error" not in r.stderr, r.stdout + r.stderr
+
+
+def test_block_schedule_under_sanitizers(tmp_path):
+    csrc = os.path.join(ROOT, "paper_2407_19987_amd", "csrc")
+    exe = str(tmp_path / "schedule_driver")
+    _run(["g++", "-std=c++17", *SAN, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", csrc,
+          os.path.join(csrc, "schedule.cpp"), os.path.join(HERE, "sanitize", "schedule_driver.cpp"), "-o", exe],
+         tmp_path)
     r = subprocess.run([exe], capture_output=True, text=True, env=ENV)
     assert r.returncode == 0 and "ERROR" not in r.stderr and "runtime error" not in r.stderr, r.stdout + r.stderr
