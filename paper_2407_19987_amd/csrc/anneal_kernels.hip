@@ -172,10 +172,14 @@ __global__ __launch_bounds__(64 * CS) void anneal_kernel(AnnealParams p) {
       if (sl.c < 0) return;
       while (sl.s > cs_cur) end_sweep(cs_cur++);
       if constexpr (decltype(restage)::value) {
-        // entering a metadata block: stage the block after it (the producer is
-        // fewer than kMetaBlock chunks ahead, so that buffer is free)
+        // entering a metadata block: stage the block after it into the buffer
+        // of the block before, once every wave has consumed that block (the
+        // first barrier; the producers are fewer than kMetaBlock chunks ahead,
+        // so none of them reads it either), and before any producer reaches
+        // the staged block (the second)
         if (sl.c % kMetaBlock == 0 && sl.c / kMetaBlock < nblk) {
           const long long gb = (long long)sl.s * nblk + sl.c / kMetaBlock + 1;
+          lds_barrier();
           if (gb < (long long)S * nblk) stage_meta((int)(gb % nblk), (int)(gb & 1));
           lds_barrier();
         }

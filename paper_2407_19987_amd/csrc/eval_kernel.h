@@ -128,10 +128,14 @@ __global__ __launch_bounds__(64 * NW) void eval_kernel(EvalParams p) {
   auto consume = [&](ESlot& sl, auto restage) {
     if (sl.c < 0) return;
     if constexpr (decltype(restage)::value) {
-      // entering a metadata block: stage the block after the next one's
-      // successor buffer (the producer is fewer than a block ahead)
+      // entering a metadata block: stage the block after it into the buffer
+      // of the block before, once every wave has consumed that block (the
+      // first barrier; the producer is fewer than a block ahead, so it does
+      // not read it either), and before any producer reaches the staged
+      // block (the second)
       if (sl.c % kEvalMetaBlock == 0) {
         const int nb = sl.c / kEvalMetaBlock + 1;
+        lds_barrier();
         if (nb < nblk) stage_meta(nb);
         lds_barrier();
       }

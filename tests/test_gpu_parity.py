@@ -130,6 +130,30 @@ def test_ragged_sizes(env, n, k, prec):
     np.testing.assert_array_equal(e, oracle.energy(c, bits))
 
 
+@pytest.mark.parametrize("prec,n,B", [(0, 80, 1024), (5, 80, 1024), (3, 100, 512)])
+def test_restaged_chunk_metadata(env, prec, n, B):
+    """Order-4 instances on 80 and 100 variables: their field and energy
+    layouts hold more than two blocks of chunk metadata (1024 chunks each; an
+    INT8X4 chunk holds twice the rows), so the kernel restages the metadata in
+    LDS while the stream runs, and each block's buffer is refilled only once
+    every wave of the work-group has left it.  Bit-exact against the oracle,
+    twice in a row."""
+    hobo, _ = env
+    terms = _int_instance(n, n, 4, dens=0.1, lo=-3, hi=3)
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    assert t.layout_info(hobo.FN_FIELDS, prec).chunks > 2 * 1024
+    assert t.layout_info(hobo.FN_ENERGY, prec).chunks > 2 * 1024
+    bits = W.pack_bits(W.random_states(n, B, seed=n))
+    e_ref = oracle.energy(c, bits)
+    de_ref = oracle.fields(c, bits)[1]
+    for _ in range(2):
+        np.testing.assert_array_equal(gpu_energy(env, t, bits, prec), e_ref)
+        de, e = gpu_fields(env, t, bits, prec)
+        np.testing.assert_array_equal(de, de_ref)
+        np.testing.assert_array_equal(e, e_ref)
+
+
 def test_intenc4_int8_bit_exact(env):
     """Integer-encoded order 4 (coefficients up to ~2^25): only INT8X4 is exact."""
     hobo, _ = env
