@@ -750,7 +750,12 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     pbits[2] = P.seed;
     pbits[3] = ((uint64_t)(uint32_t)P.sweeps << 32) | (uint32_t)P.precision;
     pbits[4] = ((uint64_t)(uint32_t)P.init << 32) | ((uint32_t)P.proposal << 8) | (uint32_t)P.waves_per_block;
-    pbits[5] = ((uint64_t)(uint32_t)P.first_sweep << 32) | (uint32_t)L;
+    // the first sweep only sets the plans' sweep offset and the uploaded
+    // inverse temperatures, which a non-captured setup takes per call (so
+    // consecutive windows of one schedule reuse the setup); a captured graph
+    // holds them
+    const uint32_t fs_key = launch_mode == HOBO_LAUNCH_GRAPH ? (uint32_t)P.first_sweep : 0u;
+    pbits[5] = ((uint64_t)fs_key << 32) | (uint32_t)L;
     pbits[6] = ((uint64_t)(uint32_t)P.continue_best << 32) | (uint32_t)P.algorithm;
     for (auto v : pbits) key.push_back(v);
   }
@@ -1007,6 +1012,16 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
   int s = HOBO_OK;
   if (launch_mode == HOBO_LAUNCH_GRAPH) {
     return hip_status(hipGraphLaunch(ent->exec, st), "hipGraphLaunch");
+  }
+  if (!ent->plans.empty() && ent->plans[0].s_first != P.first_sweep) {
+    // a setup built for another window of the schedule: this call's sweep
+    // offset and inverse temperatures (uploaded in stream order, after the
+    // previous call's kernels have read theirs)
+    for (auto& pl : ent->plans) pl.s_first = P.first_sweep;
+    ent->beta = beta;
+    if (hobo_status hs = hip_status(hipMemcpyAsync(ent->tb.d_beta, beta.data(), beta.size() * 8,
+                                                   hipMemcpyHostToDevice, st), "inverse temperature upload"))
+      return hs;
   }
   for (size_t k = 0; k < ent->plans.size() && s == HOBO_OK; ++k) s = enqueue_plan(*ent, ent->plans[k], stream, &err);
   if (s) return fail(s, err);
