@@ -47,6 +47,14 @@ hobo_status need_device() {
 
 // inverse temperature of sweep s of an L-sweep geometric schedule,
 // T_s = T_0 (T_end / T_0)^(s / (L - 1)) (Sec. II.D.1 reading), beta_s = 1 / T_s
+// The blocked annealer completes a field from the couplings (sum_b x_b H_ab
+// over the block, with the block's triples counted twice and taken back
+// once), so its FP32 partial sums reach up to three times the variable's
+// sum |w|: integer fields stay exact while that is below 2^24.
+bool blocked_exact(const hobo::Tensor& t) {
+  return !t.integer || t.var_abs_max * 3 < ((unsigned __int128)1 << 24);
+}
+
 double schedule_beta(double t_start, double t_end, int64_t s, int64_t L) {
   const double T = L == 1 ? t_start : t_start * std::pow(t_end / t_start, (double)s / (double)(L - 1));
   return 1.0 / T;
@@ -374,7 +382,7 @@ hobo_status hobo_tensor_layout_info(hobo_tensor* t, int32_t fn, int32_t precisio
   }
   if (hobo_status s = need_device()) return s;
   int mode = fn == 1 ? hobo::M_ENERGY : fn == 2 ? hobo::M_FIELDS : hobo::M_SLABS;
-  if (fn == 4 && t->t.order <= 3 && precision != HOBO_PREC_INT8X4) mode = hobo::M_BLOCKS;
+  if (fn == 4 && t->t.order <= 3 && precision != HOBO_PREC_INT8X4 && blocked_exact(t->t)) mode = hobo::M_BLOCKS;
   hobo::Packed* pk;
   if (int s = hobo::get_packed(&t->t, mode, precision, &pk, &err)) return fail(s, err);
   const int64_t k_rows = precision == HOBO_PREC_INT8X4 ? 64 : 32;
@@ -415,7 +423,7 @@ hobo_status hobo_tensor_prepare(hobo_tensor* t, uint32_t fn_mask, uint32_t prec_
       if (int s = hobo::get_packed(&t->t, hobo::M_FIELDS, p, &pk, &err)) return fail(s, err);
     if (fn_mask & 4u) {
       if (int s = hobo::get_packed(&t->t, hobo::M_SLABS, p, &pk, &err)) return fail(s, err);
-      if (t->t.order <= 3 && p != HOBO_PREC_INT8X4)
+      if (t->t.order <= 3 && p != HOBO_PREC_INT8X4 && blocked_exact(t->t))
         if (int s = hobo::get_packed(&t->t, hobo::M_BLOCKS, p, &pk, &err)) return fail(s, err);
     }
   }
@@ -613,7 +621,11 @@ hobo_status hobo_anneal_batch(hobo_tensor* const* tensors, int32_t n_instances, 
     const bool can = tensors[j]->t.order <= 3 && P.precision != HOBO_PREC_INT8X4;
     if (P.algorithm == HOBO_ANNEAL_BLOCKS && !can)
       return fail(HOBO_ERR_UNSUPPORTED, "the blocked annealer covers orders up to 3 in FP32 / BF16 precisions");
-    blocked[(size_t)j] = P.algorithm == HOBO_ANNEAL_SLABS ? 0 : (can ? 1 : 0);
+    const bool exact = blocked_exact(tensors[j]->t);
+    if (P.algorithm == HOBO_ANNEAL_BLOCKS && !exact)
+      return fail(HOBO_ERR_RANGE, "integer tensor too large for the blocked annealer's exact FP32 fields "
+                                  "(3 x the largest per-variable sum |w| must stay below 2^24)");
+    blocked[(size_t)j] = P.algorithm == HOBO_ANNEAL_SLABS ? 0 : (can && exact ? 1 : 0);
   }
   if (hobo_status s = need_device()) return s;
   hipStream_t st = (hipStream_t)stream;

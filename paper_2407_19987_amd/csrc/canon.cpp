@@ -209,8 +209,10 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
   t->w_f.clear();
   t->n_per_order.assign((size_t)k + 1, 0);
   t->abs_sum = 0;
+  t->var_abs_max = 0;
   t->w_lo = t->w_hi = 0;
   t->row_norm.assign((size_t)n_vars, 0.0);
+  std::vector<unsigned __int128> var_abs(integer ? (size_t)n_vars : 0, 0);
   for (size_t s : order) {
     const std::string& key = keys[s];
     for (char c : key) t->mono_idx.push_back((uint8_t)c);
@@ -222,11 +224,13 @@ int canonicalize(int n_vars, int max_order, int64_t n_terms, const int64_t* term
     if (integer) {
       const __int128 v = acc_i[s];
       t->abs_sum += (unsigned __int128)(v < 0 ? -v : v);
+      for (char c : key) var_abs[(uint8_t)c] += (unsigned __int128)(v < 0 ? -v : v);
       t->w_lo = std::min(t->w_lo, acc_i[s]);
       t->w_hi = std::max(t->w_hi, acc_i[s]);
     }
     for (char c : key) t->row_norm[(uint8_t)c] += w * w;
   }
+  for (const auto& v : var_abs) t->var_abs_max = std::max(t->var_abs_max, v);
   t->row_norm_max = 0.0;
   for (auto& v : t->row_norm) {
     v = std::sqrt(v);

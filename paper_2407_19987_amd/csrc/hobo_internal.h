@@ -162,6 +162,7 @@ struct Tensor {
   double offset_f = 0.0;
   std::vector<int64_t> n_per_order;  // [order+1]
   unsigned __int128 abs_sum = 0;     // integer tensors: sum |w| (exact)
+  unsigned __int128 var_abs_max = 0; // integer tensors: max over variables i of sum |w| over monomials with i
   int64_t w_lo = 0, w_hi = 0;        // integer tensors: smallest and largest weight
   double row_norm_max = 0.0;
   std::vector<double> row_norm;  // ||H_i||_2 over monomials containing i

@@ -199,6 +199,31 @@ def test_trajectory_identity_long_chunk_list(env, prec):
     assert_same(g, o)
 
 
+def test_blocked_exactness_bound_falls_back_to_slabs(env):
+    """The blocked annealer completes a field from the couplings, so its FP32
+    partial sums reach three times a variable's sum |w|.  An integer instance
+    whose variable 0 carries sum |w| of about 6.8e6 (three times that is past
+    2^24, the total stays below it): the default algorithm takes the per-bit
+    kernel and follows the oracle's chain exactly, and asking for the blocked
+    one is refused with HOBO_ERR_RANGE."""
+    hobo, _ = env
+    rng = np.random.default_rng(77)
+    n = 20
+    subs = [np.array([[0, b, c] for b in range(1, n) for c in range(b + 1, n)]), W.lex_subsets(n, 2)]
+    co = [rng.choice([-1, 1], size=len(subs[0])) * rng.integers(38000, 42000, size=len(subs[0])),
+          rng.integers(-50, 51, size=len(subs[1]))]
+    terms = W.subsets_to_terms(n, [subs[1], subs[0]], [co[1], co[0]], True)
+    var0 = int(np.abs(co[0]).sum())
+    assert 3 * var0 >= 1 << 24 and int(np.abs(terms.coeff).sum()) < 1 << 24
+    c = oracle.canonicalize(terms)
+    t = hobo.Tensor.from_terms(terms)
+    o = oracle.anneal(c, 48, 6, 3.0e4, 1.0e3, seed=9)
+    assert_same(run_gpu(env, t, 48, 6, 3.0e4, 1.0e3, seed=9, prec=0)[0], o)
+    with pytest.raises(hobo.HoboError) as ei:
+        run_gpu(env, t, 48, 6, 3.0e4, 1.0e3, seed=9, prec=0, algo=BLOCKS)
+    assert ei.value.code == hobo.ERR_RANGE
+
+
 def test_restaged_chunk_metadata_repeatable(env):
     """Order-4 real instances of the mixed family (N = 85 to 95) whose slabs
     hold thousands of chunks, 1024 replicas each: the chunk metadata is
