@@ -649,10 +649,12 @@ def annealer_digest() -> str:
 def read_cu_path(precision, B, S, launches, anneal_ms):
     """The annealer's measured bound: each compute unit's vector-memory
     return path, which carries the coefficient tiles into registers.  The
-    L1 -> L2 read requests (128 B) per launch and the data-return unit's busy
-    share come from the committed counter summary of the same annealer sources;
-    the bytes are taken over this run's launch time, against 64 B per clock
-    per CU (256 CUs, 2.4 GHz)."""
+    bytes returned to registers per launch (from the schedule, checked
+    against the counted vector-memory reads), the L1 -> L2 read requests
+    (128 B) and the data-return unit's busy share come from the committed
+    counter summary of the same annealer sources; the bytes are taken over
+    this run's launch time, against 64 B per clock per CU (256 CUs,
+    2.4 GHz)."""
     try:
         import re
 
@@ -660,16 +662,19 @@ def read_cu_path(precision, B, S, launches, anneal_ms):
         txt = open(prof).read()
         if annealer_digest() not in txt:
             return None
+        ret = float(re.search(r"\*\*([0-9.e+]+) bytes returned to registers per\s+launch\*\*", txt).group(1))
         req = float(re.search(r"`TCP_TCC_READ_REQ_sum`[^|]*\| ([0-9.e+]+) \|", txt).group(1))
         busy = float(re.search(r"\| data return \(TD\) busy \| ([0-9.]+) %", txt).group(1)) / 100
         wait = float(re.search(r"stalled waiting for the L1[^|]*\| ([0-9.]+) %", txt).group(1)) / 100
         if precision != "fp16x2" or B != REPLICAS or S != SWEEPS or launches != 4:
             return None
-        tbps = req * 128 / (anneal_ms / launches * 1e-3) / 1e12
+        sec = anneal_ms / launches * 1e-3
+        tbps = ret / sec / 1e12
         peak = 64 * 256 * 2.4e9 / 1e12
         return {"resource": "per-CU vector-memory return path (coefficient tiles into registers)",
                 "achieved": tbps, "peak": peak, "unit": "TB/s", "frac": tbps / peak,
-                "l1_fill_requests_per_launch": req, "data_return_busy": busy, "data_return_waiting_on_l1": wait,
+                "returned_bytes_per_launch": ret, "l1_fill_tbps": req * 128 / sec / 1e12,
+                "data_return_busy": busy, "data_return_waiting_on_l1": wait,
                 "source": "profiles/anneal_block_cu_path_order3_n128_fp16x2.md"}
     except (OSError, AttributeError, ValueError):
         return None
