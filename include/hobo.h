@@ -206,7 +206,11 @@ enum { HOBO_INIT_RANDOM = 0, HOBO_INIT_GIVEN = 1 };
 enum { HOBO_PROPOSAL_METROPOLIS = 0, HOBO_PROPOSAL_MASKED = 1, HOBO_PROPOSAL_LEARNED = 2 };
 enum { HOBO_LAUNCH_PER_INSTANCE = 0, HOBO_LAUNCH_PERSISTENT = 1, HOBO_LAUNCH_GRAPH = 2 };
 /* annealing kernels: AUTO picks BLOCKS where it applies (order <= 3, FP32 /
- * BF16X2 / BF16X3 / FP16X2), else SLABS.  Both run the same chain. */
+ * BF16X2 / BF16X3 / FP16X2, and for integer tensors 3 x the largest sum |w|
+ * over the monomials of one variable below 2^24, so that its FP32 fields stay
+ * exact), else SLABS.  Both run the same chain.  BLOCKS asked for where it
+ * does not apply: HOBO_ERR_UNSUPPORTED (order, precision) or HOBO_ERR_RANGE
+ * (the integer bound). */
 enum { HOBO_ANNEAL_AUTO = 0, HOBO_ANNEAL_SLABS = 1, HOBO_ANNEAL_BLOCKS = 2 };
 
 typedef struct {
