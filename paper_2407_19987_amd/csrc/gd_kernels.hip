@@ -19,8 +19,8 @@
 
 namespace hobo {
 
-constexpr int kGDWaves = 4;      // waves per work-group
-constexpr int kGDSliceVars = 8;  // variables per work-group (grid.y covers N)
+constexpr int kGDWaves = 16;     // waves per work-group (one variable each)
+constexpr int kGDSliceVars = 16; // variables per work-group (grid.y covers N)
 
 // MAXO: largest monomial order of the tensor (records carry up to MAXO - 1
 // other variables), so the product loop has a fixed trip count with
@@ -73,11 +73,14 @@ __global__ __launch_bounds__(64 * kGDWaves) void gd_step_kernel(GDArgs a) {
       const u4 nxt = load(r + 64);
       const int cnt = r1 - r < 64 ? r1 - r : 64;
       int k = 0;
-      // four records at a time: their LDS reads overlap; the sum keeps the
+      // eight records at a time: their LDS reads overlap; the sum keeps the
       // record order
-      for (; k + 4 <= cnt; k += 4) {
-        const double t0 = term(cur, k), t1 = term(cur, k + 1), t2 = term(cur, k + 2), t3 = term(cur, k + 3);
-        g = __dadd_rn(__dadd_rn(__dadd_rn(__dadd_rn(g, t0), t1), t2), t3);
+      for (; k + 8 <= cnt; k += 8) {
+        double t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = term(cur, k + q);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) g = __dadd_rn(g, t[q]);
       }
       for (; k < cnt; ++k) g = __dadd_rn(g, term(cur, k));
       cur = nxt;
