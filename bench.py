@@ -513,6 +513,9 @@ def mixed(hobo, W, torch, dev, mi, mb, msw, tune):
            "per_instance_ms": res["per_instance"]["ms"], "persistent_graph_ms": res["persistent_graph"]["ms"],
            "speedup": res["per_instance"]["ms"] / res["persistent_graph"]["ms"],
            "replica_sweeps_per_s": mi * mb * msw / (res["persistent_graph"]["ms"] / 1e3),
+           # useful work: each order-r monomial feeds r fields, 2 flops each, per replica-sweep
+           "useful_tflops": sum(2 * sum(r * int(c) for r, c in enumerate(mt.info().n_per_order)) for mt in mts)
+                            * mb * msw / (res["persistent_graph"]["ms"] / 1e3) / 1e12,
            "identical_results": bool(np.array_equal(res["per_instance"]["best"], res["persistent_graph"]["best"])),
            "host_build_pack_s": host_s, "sample": f"instances 0..{mi - 1} of the mixed family (master seed 0)"}
     if tune:
