@@ -232,7 +232,11 @@ typedef struct {
                               grouped, so decisions within rounding of a tie may
                               differ between widths. */
   int32_t algorithm;   /* HOBO_ANNEAL_AUTO | SLABS | BLOCKS */
-  int32_t first_sweep; /* this call runs sweeps first_sweep .. first_sweep+sweeps-1 */
+  int32_t first_sweep; /* this call runs sweeps first_sweep .. first_sweep+sweeps-1;
+                          consecutive windows of one schedule with the same
+                          buffers reuse one setup (PER_INSTANCE / PERSISTENT),
+                          so such calls must be ordered, as their shared
+                          buffers already require */
   int32_t schedule_sweeps; /* L, length of the whole schedule; 0 = sweeps (first_sweep
                               must then be 0) */
   int32_t continue_best; /* 1: the best states start from best_x_out (their energies
