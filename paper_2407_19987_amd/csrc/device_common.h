@@ -305,9 +305,9 @@ struct TermJob {             // one instance's term-loop energy of a batch
 };
 // Bit-sliced term sums.  For each group of 64 replicas term_masks stores,
 // per variable v, the 64-bit mask whose bit r is x_{64g + r, v}.  A
-// monomial's mask over the group is the AND of its variables' masks, formed
-// once per wave from scalar loads, and lane r adds w_S when bit r is set;
-// the monomials of a group are added in list order.
+// monomial's mask over the group is the AND of its variables' masks, and
+// lane r adds w_S when bit r is set; the monomials of a group are added in
+// list order.
 __host__ __device__ inline size_t term_mask_offset(int n_mono, long long B) {  // bytes into the workspace
   return ((size_t)term_groups(n_mono) * (size_t)B * 8 + 255) & ~(size_t)255;
 }
@@ -335,63 +335,94 @@ __device__ inline void term_masks(const TermJob& J, int rowblock) {
   }
 }
 
-__device__ inline void term_partial(const TermJob& J, int rowblock, int grp) {
+// One 64-replica group per wave; the group's variable masks are copied to LDS.
+// Lanes form 64 monomials' masks at once (lane q: monomial m + q, the AND of
+// its seven index slots' masks, repeats included), then the wave walks those
+// 64 monomials in list order: the monomial's mask, read from its lane, is the
+// exec mask of one FP64 (int64) add of its weight, so lane r adds w_S exactly
+// when bit r is set, in the same order as a per-lane loop over the list.
+template <bool INT>
+__device__ inline void term_walk(const TermJob& J, const unsigned long long* sm, int m0, int m1, void* acc_out) {
   const int lane = threadIdx.x & 63;
-  const long long g = (long long)rowblock * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  typedef const __attribute__((address_space(4))) u4* ConstU4;
+  const ConstU4 srec = (ConstU4)J.rec;
+  const u4* vrec = reinterpret_cast<const u4*>(J.rec);
+  double sf = 0.0;
+  long long si = 0;
+  auto add = [&](unsigned long long mk, const u4& r) {
+    const unsigned long long wb = ((unsigned long long)r[3] << 32) | r[2];
+    unsigned long long save;
+    if (INT)
+      asm volatile("s_and_saveexec_b64 %0, %2\n\tv_lshl_add_u64 %1, %1, 0, %3\n\ts_mov_b64 exec, %0"
+                   : "=&s"(save), "+v"(si) : "s"(mk), "s"(wb));
+    else
+      asm volatile("s_and_saveexec_b64 %0, %2\n\tv_add_f64 %1, %3, %1\n\ts_mov_b64 exec, %0"
+                   : "=&s"(save), "+v"(sf) : "s"(mk), "s"(__longlong_as_double((long long)wb)));
+  };
+  for (int m = m0; m < m1; m += 64) {
+    const int cnt = m1 - m < 64 ? m1 - m : 64;
+    unsigned long long mk = 0;
+    if (lane < cnt) {
+      const u4 r = vrec[m + lane];
+      mk = sm[r[0] & 0xFFu] & sm[(r[0] >> 8) & 0xFFu] & sm[(r[0] >> 16) & 0xFFu] & sm[r[0] >> 24] &
+           sm[r[1] & 0xFFu] & sm[(r[1] >> 8) & 0xFFu] & sm[(r[1] >> 16) & 0xFFu];
+    }
+    const unsigned lo = (unsigned)mk, hi = (unsigned)(mk >> 32);
+    auto mask_at = [&](int q) {
+      return ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)hi, q) << 32) |
+             (unsigned)__builtin_amdgcn_readlane((int)lo, q);
+    };
+    if (cnt == 64) {  // the next four weights load while the current four are added
+      u4 n0 = srec[m], n1 = srec[m + 1], n2 = srec[m + 2], n3 = srec[m + 3];
+#pragma unroll
+      for (int q = 0; q < 64; q += 4) {
+        u4 ra = n0, rb = n1, rc = n2, rd = n3;
+        asm volatile("" : "+s"(ra), "+s"(rb), "+s"(rc), "+s"(rd));
+        if (q + 4 < 64) { n0 = srec[m + q + 4]; n1 = srec[m + q + 5]; n2 = srec[m + q + 6]; n3 = srec[m + q + 7]; }
+        add(mask_at(q), ra);
+        add(mask_at(q + 1), rb);
+        add(mask_at(q + 2), rc);
+        add(mask_at(q + 3), rd);
+      }
+    } else {
+      for (int q = 0; q < cnt; ++q) {
+        const u4 r = srec[m + q];
+        add(mask_at(q), r);
+      }
+    }
+  }
+  if (INT)
+    *static_cast<long long*>(acc_out) = si;
+  else
+    *static_cast<double*>(acc_out) = sf;
+}
+
+__device__ inline void term_partial(const TermJob& J, int rowblock, int grp) {
+  __shared__ unsigned long long sm_masks[4][kMaxVars];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long g = (long long)rowblock * 4 + wv;
   if (g * 64 >= J.B) return;
   const long long b = g * 64 + lane;
   const int m0 = grp * kTermGroup;
   const int m1 = m0 + kTermGroup < J.n_mono ? m0 + kTermGroup : J.n_mono;
-  typedef const __attribute__((address_space(4))) unsigned long long* ConstU64;
-  typedef const __attribute__((address_space(4))) u4* ConstU4;
-  const ConstU64 masks =
-      (ConstU64)(static_cast<const char*>(J.part) + term_mask_offset(J.n_mono, J.B)) + g * 64 * J.W;
-  const ConstU4 rec = (ConstU4)J.rec;
-  double sf = 0.0;
-  long long si = 0;
-  // one monomial's mask over the 64 replicas: the first three variables in
-  // independent loads (unused slots repeat idx[0], so shorter monomials AND
-  // the same mask again), any further ones after
-  auto mask3 = [&](const u4& r) {
-    return masks[r[0] & 0xFFu] & masks[(r[0] >> 8) & 0xFFu] & masks[(r[0] >> 16) & 0xFFu];
-  };
-  auto tail = [&](const u4& r, unsigned long long mk) {
-    const unsigned len = r[1] >> 24;
-    for (unsigned q = 3; q < len; ++q) mk &= masks[((q < 4 ? r[0] : r[1]) >> (8 * (q & 3))) & 0xFFu];
-    return mk;
-  };
-  auto mask_of = [&](const u4& r) { return tail(r, mask3(r)); };
-  auto add = [&](const u4& r, unsigned long long mk) {
-    const bool on = ((mk >> lane) & 1ull) != 0;
-    const unsigned long long wb = ((unsigned long long)r[3] << 32) | r[2];
-    if (J.integer)
-      si += on ? (long long)wb : 0ll;
-    else
-      sf += on ? __longlong_as_double((long long)wb) : 0.0;
-  };
-  int m = m0;
-  for (; m + 4 <= m1; m += 4) {  // four records, then their masks, in flight together
-    const u4 ra = rec[m], rb = rec[m + 1], rc = rec[m + 2], rd = rec[m + 3];
-    unsigned long long ka = mask3(ra), kb = mask3(rb), kc = mask3(rc), kd = mask3(rd);
-    asm volatile("" : "+s"(ka), "+s"(kb), "+s"(kc), "+s"(kd));  // all twelve loads before any tail branch
-    ka = tail(ra, ka);
-    kb = tail(rb, kb);
-    kc = tail(rc, kc);
-    kd = tail(rd, kd);
-    add(ra, ka);
-    add(rb, kb);
-    add(rc, kc);
-    add(rd, kd);
-  }
-  for (; m < m1; ++m) {
-    const u4 r = rec[m];
-    add(r, mask_of(r));
-  }
-  if (b < J.B) {
-    if (J.integer)
-      reinterpret_cast<long long*>(J.part)[(long long)grp * J.B + b] = si;
-    else
-      reinterpret_cast<double*>(J.part)[(long long)grp * J.B + b] = sf;
+  const unsigned long long* masks =
+      reinterpret_cast<const unsigned long long*>(static_cast<const char*>(J.part) + term_mask_offset(J.n_mono, J.B)) +
+      g * 64 * J.W;
+  unsigned long long* sm = sm_masks[wv];
+  for (int w = 0; w < J.W; ++w) sm[64 * w + lane] = masks[64 * w + lane];
+  // the wave's own LDS copy: its writes land before its reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (J.integer) {
+    long long si;
+    term_walk<true>(J, sm, m0, m1, &si);
+    if (b < J.B) reinterpret_cast<long long*>(J.part)[(long long)grp * J.B + b] = si;
+  } else {
+    double sf;
+    term_walk<false>(J, sm, m0, m1, &sf);
+    if (b < J.B) reinterpret_cast<double*>(J.part)[(long long)grp * J.B + b] = sf;
   }
 }
 

@@ -372,6 +372,45 @@ def test_fp16x2_wide_dynamic_range(env):
     assert (np.abs(de.astype(np.float64) - de_ref) <= 1e-5 * np.maximum(np.abs(de_ref), fs) + 2.0 ** -39 * wmax * n * n).all()
 
 
+def _orders_to_seven(seed, n, integer):
+    """Every order from 1 to the engine's limit of 7 on n variables: all
+    singles and pairs, plus 1500 distinct random subsets of each order 3..7;
+    real coefficients are FP32-rounded N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    subs = [W.lex_subsets(n, 1), W.lex_subsets(n, 2)]
+    for r in range(3, 8):
+        s = np.unique(np.sort(np.array([rng.choice(n, r, replace=False) for _ in range(1500)]), axis=1), axis=0)
+        subs.append(s)
+    if integer:
+        co = [rng.integers(-9, 10, size=len(s)) for s in subs]
+    else:
+        co = [rng.standard_normal(len(s)).astype(np.float32).astype(np.float64) for s in subs]
+    return W.subsets_to_terms(n, subs, co, integer)
+
+
+@pytest.mark.parametrize("integer", [True, False])
+@pytest.mark.parametrize("n,B", [(256, 203), (130, 4100), (40, 1)])
+def test_fp64_term_sums_orders_to_seven(env, integer, n, B):
+    """The FP64 / int64 term kernels (start energies, rescoring) against the
+    oracle's energy: monomials of every order up to 7 (all seven index slots
+    of a record in use), several 4096-monomial groups with a ragged last
+    64-monomial chunk, states in four 64-bit words (n = 256) and batches that
+    end inside a 64-replica group.  Integer sums are exact; FP64 sums agree to
+    1e-12 of max(|E|, s(x))."""
+    terms = _orders_to_seven(n + B, n, integer)
+    c = oracle.canonicalize(terms)
+    hobo, _ = env
+    t = hobo.Tensor.from_terms(terms)
+    assert t.n_monomials > 4096 and t.n_monomials % 64 != 0
+    bits = W.pack_bits(W.random_states(n, B, seed=n * 7 + B))
+    got = gpu_energy(env, t, bits, 4)
+    want = oracle.energy(c, bits)
+    if integer:
+        np.testing.assert_array_equal(got, want)
+    else:
+        assert _rel_err(got, want, oracle.active_scale(c, bits)).max() <= 1e-12
+
+
 @pytest.mark.parametrize("prec", [5, 3])
 def test_maximum_variable_count(env, prec):
     """N = 256, the engine's limit (four 64-bit words per state): order 2
