@@ -27,7 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.
 # so are both annealers
 SOURCES = [("anneal_kernels.hip", "", []), ("anneal_block.hip", "", []), ("mlp_kernels.hip", "", []),
            ("eval_kernels.hip", "", []), ("timing.hip", "", []), ("pack.cpp", "", []), ("canon.cpp", "", []), ("results.cpp", "", []), ("tt.cpp", "", []), ("tt_kernels.hip", "", []), ("gd.cpp", "", []), ("schedule.cpp", "", []),
-           ("gd_kernels.hip", "", []),
+           ("gd_kernels.hip", "", ["-ffp-contract=off"]),  # separately rounded FP64 steps
            ("abi.cpp", "", [])] + [
     ("eval_prec.hip", f"p{p}", [f"-DHOBO_EVAL_PREC={p}"]) for p in (0, 1, 2, 3, 5)] + [
     ("anneal_block.hip", f"p{p}", [f"-DHOBO_BLOCK_PREC={p}"]) for p in (0, 1, 2, 5)] + [

@@ -6,9 +6,11 @@
 // read and write consecutive doubles.  A work-group takes 64 replicas and a
 // slice of the variables: it stages the replicas' whole p in LDS ([N][64]
 // doubles), then each wave walks the record lists of its variables; every
-// lane reads the same record (wave-uniform loads) and its own p entries
-// (consecutive LDS doubles).  FP64 with separately rounded products and sums
-// (no fused multiply-add), the order of the records being the monomial order.
+// lane reads the same record (scalar loads) and its own p entries
+// (consecutive LDS doubles).  FP64 with separately rounded products and sums,
+// the order of the records being the monomial order: this file is built with
+// -ffp-contract=off (HIP's __dmul_rn and __dadd_rn are plain operators, and
+// the default contraction would fuse them into multiply-adds).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -45,45 +47,50 @@ __global__ __launch_bounds__(64 * kGDWaves) void gd_step_kernel(GDArgs a) {
     const int r0 = __builtin_amdgcn_readfirstlane(gld(a.ptr + i));
     const int r1 = __builtin_amdgcn_readfirstlane(gld(a.ptr + i + 1));
     double g = 0.0;
-    // 64 records per round: lane l loads record r + l (one coalesced load,
-    // the next round's issued before this one is used); each record's fields
-    // are then broadcast from its lane into scalar registers
-    auto load = [&](int r) {
-      u4 v = u4{0u, 0u, 0u, 0u};
-      if (r + lane < r1) v = gld(reinterpret_cast<const u4*>(a.rec) + r + lane);
-      return v;
-    };
-    // product of record k of the round: its weight times the other variables' p
-    auto term = [&](const u4& cur, int k) {
-      const unsigned wlo = __builtin_amdgcn_readlane(cur[0], k), whi = __builtin_amdgcn_readlane(cur[1], k);
-      const unsigned no = __builtin_amdgcn_readlane(cur[2], k), o47 = __builtin_amdgcn_readlane(cur[3], k);
-      double prod = __hiloint2double((int)whi, (int)wlo);
-      const int nn = (int)(no & 0xFFu);
+    // the records come through scalar loads, eight at a time, the next eight
+    // issued before the current ones are used; the lanes read their own p
+    // entries (consecutive LDS doubles)
+    typedef const __attribute__((address_space(4))) u4* ConstU4;
+    const ConstU4 srec = (ConstU4)a.rec;
+    // product of a record: its weight times the other variables' p.  Every
+    // slot is read (unused slots hold variable 0) and multiplies by 1.0, which
+    // is exact, so the reads need no branch and overlap
+    auto term = [&](const u4& rc) {
+      double prod = __hiloint2double((int)rc[1], (int)rc[0]);
+      const int nn = (int)(rc[2] & 0xFFu);
 #pragma unroll
       for (int q = 0; q < MAXO - 1; ++q) {
-        if (q < nn) {
-          const unsigned o = q < 3 ? (no >> (8 * (q + 1))) & 0xFFu : (o47 >> (8 * (q - 3))) & 0xFFu;
-          prod = __dmul_rn(prod, sp[o * 64 + lane]);
-        }
+        const unsigned o = q < 3 ? (rc[2] >> (8 * (q + 1))) & 0xFFu : (rc[3] >> (8 * (q - 3))) & 0xFFu;
+        const double f = sp[o * 64 + lane];
+        prod = __dmul_rn(prod, q < nn ? f : 1.0);
       }
       return prod;
     };
-    u4 cur = load(r0);
-    for (int r = r0; r < r1; r += 64) {
-      const u4 nxt = load(r + 64);
-      const int cnt = r1 - r < 64 ? r1 - r : 64;
-      int k = 0;
-      // eight records at a time: their LDS reads overlap; the sum keeps the
-      // record order
-      for (; k + 8 <= cnt; k += 8) {
+    int r = r0;
+    if (r + 8 <= r1) {
+      u4 nx[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) nx[q] = srec[r + q];
+      for (; r + 8 <= r1; r += 8) {
+        u4 cu[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cu[q] = nx[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) asm volatile("" : "+s"(cu[q]));
+        if (r + 16 <= r1)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) nx[q] = srec[r + 8 + q];
+        // the eight products' LDS reads overlap; the sum keeps the record order
         double t[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) t[q] = term(cur, k + q);
+        for (int q = 0; q < 8; ++q) t[q] = term(cu[q]);
 #pragma unroll
         for (int q = 0; q < 8; ++q) g = __dadd_rn(g, t[q]);
       }
-      for (; k < cnt; ++k) g = __dadd_rn(g, term(cur, k));
-      cur = nxt;
+    }
+    for (; r < r1; ++r) {
+      const u4 rc = srec[r];
+      g = __dadd_rn(g, term(rc));
     }
     if (live) {
       if (a.mode == 1) {
