@@ -4,8 +4,11 @@
 // evaluated left to right as a row vector v <- v M_k(x), O(d n r^2) per
 // replica instead of the dense tensor's O(n^d).  One thread per replica;
 // every lane of a wave walks the same core entries in the same order (the
-// bit only selects a zero or the vector entry), so the core loads are
-// wave-uniform and come through the scalar cache.  FP64 throughout.
+// bit only selects a zero or the vector entry).  The work-group copies each
+// core to LDS a slice of variables at a time and its four waves read the
+// rows from there (one address per wave: broadcast reads), instead of each
+// wave fetching them through the scalar cache.  FP64 throughout, one fused
+// multiply-add per (variable, row, column) in that order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -25,8 +28,15 @@ struct TTParams {
   long long off[kMaxOrder];
 };
 
+constexpr int kTTStage = 4096;  // doubles of a core slice staged in LDS (32 KB)
+
 template <int RMAX>
 __global__ __launch_bounds__(256) void tt_energy_kernel(TTParams p) {
+  // G_k[a][i0 .. i0 + ni)[c], rows (a, i) of r doubles, then RMAX zeros: a
+  // row is read whole (RMAX columns, no branch per column); the columns at or
+  // past r accumulate values that are never used
+  __shared__ double sg[kTTStage + RMAX];
+  for (int e = threadIdx.x; e < RMAX; e += blockDim.x) sg[kTTStage + e] = 0.0;
   const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = b < p.B;
   unsigned long long xw[4] = {0, 0, 0, 0};
@@ -38,21 +48,31 @@ __global__ __launch_bounds__(256) void tt_energy_kernel(TTParams p) {
   for (int k = 0; k < p.order; ++k) {
     const int r = p.ranks[k + 1];
     const double* g = p.cores + p.off[k];
+    const int ni = kTTStage / (rp * r);  // variables per slice (ranks <= 32: at least 4)
     double w[RMAX];
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) w[c] = 0.0;
-    for (int i = 0; i < p.n; ++i) {
-      const int wi = i >> 6;
-      const unsigned long long word = wi == 0 ? xw[0] : wi == 1 ? xw[1] : wi == 2 ? xw[2] : xw[3];
-      const bool on = (word >> (i & 63)) & 1ull;
+    for (int i0 = 0; i0 < p.n; i0 += ni) {
+      const int nn = p.n - i0 < ni ? p.n - i0 : ni;
+      __syncthreads();  // the previous slice has been read
+      for (int e = threadIdx.x; e < rp * nn * r; e += blockDim.x) {
+        const int a = e / (nn * r);
+        sg[e] = g[((long long)a * p.n + i0) * r + (e - a * nn * r)];
+      }
+      __syncthreads();
+      for (int ii = 0; ii < nn; ++ii) {
+        const int i = i0 + ii;
+        const int wi = i >> 6;
+        const unsigned long long word = wi == 0 ? xw[0] : wi == 1 ? xw[1] : wi == 2 ? xw[2] : xw[3];
+        const bool on = (word >> (i & 63)) & 1ull;
 #pragma unroll
-      for (int a = 0; a < RMAX; ++a) {
-        if (a < rp) {
-          const double va = on ? v[a] : 0.0;
-          const double* row = g + ((long long)a * p.n + i) * r;
+        for (int a = 0; a < RMAX; ++a) {
+          if (a < rp) {
+            const double va = on ? v[a] : 0.0;
+            const double* row = sg + (a * nn + ii) * r;
 #pragma unroll
-          for (int c = 0; c < RMAX; ++c)
-            if (c < r) w[c] = fma(va, row[c], w[c]);
+            for (int c = 0; c < RMAX; ++c) w[c] = fma(va, row[c], w[c]);
+          }
         }
       }
     }
