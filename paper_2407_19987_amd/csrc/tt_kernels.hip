@@ -65,13 +65,26 @@ __global__ __launch_bounds__(256) void tt_energy_kernel(TTParams p) {
         const int wi = i >> 6;
         const unsigned long long word = wi == 0 ? xw[0] : wi == 1 ? xw[1] : wi == 2 ? xw[2] : xw[3];
         const bool on = (word >> (i & 63)) & 1ull;
+        // rows in groups of G, each group's reads in flight together; a row
+        // of the group at or past rp reads the zeros after the slice (v[a] is
+        // +0 there and fma(+0, 0, w) is w, w being never -0)
+        constexpr int G = RMAX >= 32 ? 2 : (RMAX >= 4 ? 4 : RMAX);
 #pragma unroll
-        for (int a = 0; a < RMAX; ++a) {
-          if (a < rp) {
-            const double va = on ? v[a] : 0.0;
-            const double* row = sg + (a * nn + ii) * r;
+        for (int a0 = 0; a0 < RMAX; a0 += G) {
+          if (a0 < rp) {
+            double rw[G][RMAX];
 #pragma unroll
-            for (int c = 0; c < RMAX; ++c) w[c] = fma(va, row[c], w[c]);
+            for (int q = 0; q < G; ++q) {
+              const double* row = a0 + q < rp ? sg + ((a0 + q) * nn + ii) * r : sg + kTTStage;
+#pragma unroll
+              for (int c = 0; c < RMAX; ++c) rw[q][c] = row[c];
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+              const double va = on ? v[a0 + q] : 0.0;
+#pragma unroll
+              for (int c = 0; c < RMAX; ++c) w[c] = fma(va, rw[q][c], w[c]);
+            }
           }
         }
       }
