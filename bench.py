@@ -42,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 N_VARS, ORDER, REPLICAS, SWEEPS, T0, T1 = 128, 3, 4096, 1000, 5.0, 0.01
 PREC_OF = {"fp32": 0, "bf16x2": 1, "bf16x3": 2, "fp16x2": 5}
+ALG_OF = {"auto": 0, "slabs": 1, "blocks": 2}  # hobo_anneal_params.algorithm
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0, "fp16x2": 2500.0, "int8x4": 5000.0}
 PASSES = {"fp32": 1, "bf16x2": 2, "bf16x3": 3, "fp16x2": 2}
 DTYPE = {"fp32": "fp32", "bf16x2": "bf16", "bf16x3": "bf16", "fp16x2": "fp16"}
@@ -82,6 +83,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=SWEEPS)
     ap.add_argument("--replicas", type=int, default=REPLICAS)
     ap.add_argument("--precision", default="fp16x2", choices=list(PREC_OF))
+    ap.add_argument("--algorithm", default="auto", choices=list(ALG_OF),
+                    help="annealing kernel of the step: auto (the blocked kernel where it applies), or the "
+                         "per-bit slab kernel")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-eval-sweep", action="store_true")
@@ -149,7 +153,8 @@ def main():
         if learned is not None:
             kw = dict(mlp=learned["mlp"], tau=learned["tau"], p_floor=learned["p_floor"], refresh=learned["refresh"])
         hobo.anneal_batch(t, B, x, bx, be, sweeps=S, t_start=T0, t_end=T1, seed=42, precision=prec,
-                          init=hobo.INIT_RANDOM, trace_out=tr, launch_mode=hobo.LAUNCH_PERSISTENT, **kw)
+                          init=hobo.INIT_RANDOM, trace_out=tr, launch_mode=hobo.LAUNCH_PERSISTENT,
+                          algorithm=ALG_OF[args.algorithm], **kw)
 
     def timed(prec_name: str, warmup: int, steps: int, learned=None):
         prec = PREC_OF[prec_name]
@@ -255,8 +260,10 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(terms, S)
 
-    traffic = read_traffic(args.precision, B, S, main_res["anneal_launches"])
-    cu_path = read_cu_path(args.precision, B, S, main_res["anneal_launches"], main_res["anneal_ms"])
+    # the committed counter summaries are the blocked annealer's
+    slabs = args.algorithm == "slabs"
+    traffic = None if slabs else read_traffic(args.precision, B, S, main_res["anneal_launches"])
+    cu_path = None if slabs else read_cu_path(args.precision, B, S, main_res["anneal_launches"], main_res["anneal_ms"])
     rec = {
         "metric": "HOBO energy+ΔE evals/s; time-to-target energy, plain vs split/learned",
         "value": value,
@@ -272,9 +279,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"order-3 HOBO, N={N_VARS}, dense FP32 N(0,1)/N coefficients, B={B} replicas, "
                                f"{S} Metropolis sweeps T {T0}->{T1}, energy + fields + anneal per step",
-                   "n_vars": N_VARS, "order": ORDER, "replicas": B, "sweeps": S, "precision": args.precision},
+                   "n_vars": N_VARS, "order": ORDER, "replicas": B, "sweeps": S, "precision": args.precision,
+                   "algorithm": args.algorithm},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic, "kernel": "anneal_block_kernel",
+                     "traffic": traffic, "kernel": "anneal_kernel" if slabs else "anneal_block_kernel",
                      "flops_per_launch": flops // max(main_res["anneal_launches"], 1),
                      "avg_launch_ms": main_res["anneal_ms"] / max(main_res["anneal_launches"], 1),
                      "launches_per_step": main_res["anneal_launches"],
