@@ -349,6 +349,8 @@ __device__ inline void term_walk(const TermJob& J, const unsigned long long* sm,
   const u4* vrec = reinterpret_cast<const u4*>(J.rec);
   double sf = 0.0;
   long long si = 0;
+  // the add runs with exec = (the wave's exec) & mk and restores the saved
+  // exec in the same asm statement (the walk is in wave-uniform control flow)
   auto add = [&](unsigned long long mk, const u4& r) {
     const unsigned long long wb = ((unsigned long long)r[3] << 32) | r[2];
     unsigned long long save;
