@@ -29,7 +29,7 @@ constexpr int kGDSliceVars = 16; // variables per work-group (grid.y covers N)
 // wave-uniform guards
 template <int MAXO>
 __global__ __launch_bounds__(64 * kGDWaves) void gd_step_kernel(GDArgs a) {
-  extern __shared__ double sp[];  // [N][64]
+  extern __shared__ double sp[];  // [N][64], then a row of 64 ones
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long long b0 = (long long)blockIdx.x * 64;
   const long long b = b0 + lane;
@@ -40,6 +40,7 @@ __global__ __launch_bounds__(64 * kGDWaves) void gd_step_kernel(GDArgs a) {
     const long long bb = b0 + l;
     sp[e] = bb < a.B ? gld(a.p_in + (long long)i * a.B + bb) : 0.0;
   }
+  for (int e = threadIdx.x; e < 64; e += blockDim.x) sp[N * 64 + e] = 1.0;
   __syncthreads();
   const int i0 = blockIdx.y * kGDSliceVars;
   const int i1 = i0 + kGDSliceVars < N ? i0 + kGDSliceVars : N;
@@ -53,16 +54,17 @@ __global__ __launch_bounds__(64 * kGDWaves) void gd_step_kernel(GDArgs a) {
     typedef const __attribute__((address_space(4))) u4* ConstU4;
     const ConstU4 srec = (ConstU4)a.rec;
     // product of a record: its weight times the other variables' p.  Every
-    // slot is read (unused slots hold variable 0) and multiplies by 1.0, which
-    // is exact, so the reads need no branch and overlap
+    // slot is read, an unused one from the row of ones (the choice is made on
+    // the wave-uniform index), and multiplying by 1.0 is exact, so the reads
+    // need no branch and overlap
     auto term = [&](const u4& rc) {
       double prod = __hiloint2double((int)rc[1], (int)rc[0]);
       const int nn = (int)(rc[2] & 0xFFu);
 #pragma unroll
       for (int q = 0; q < MAXO - 1; ++q) {
         const unsigned o = q < 3 ? (rc[2] >> (8 * (q + 1))) & 0xFFu : (rc[3] >> (8 * (q - 3))) & 0xFFu;
-        const double f = sp[o * 64 + lane];
-        prod = __dmul_rn(prod, q < nn ? f : 1.0);
+        const unsigned oe = q < nn ? o : (unsigned)N;
+        prod = __dmul_rn(prod, sp[oe * 64 + lane]);
       }
       return prod;
     };
@@ -133,11 +135,11 @@ __global__ void gd_round_kernel(int N, long long B, const double* p, unsigned lo
 
 int launch_gd_step(const GDArgs& a, std::string* err) {
   const dim3 grid((unsigned)((a.B + 63) / 64), (unsigned)((a.n_vars + kGDSliceVars - 1) / kGDSliceVars));
-  const size_t lds = (size_t)a.n_vars * 64 * sizeof(double);  // up to 128 KB at N = 256
+  const size_t lds = (size_t)(a.n_vars + 1) * 64 * sizeof(double);  // up to 128.5 KB at N = 256
   static std::once_flag once;
   static hipError_t attr = hipSuccess;
   std::call_once(once, [] {
-    const int bytes = (int)(kMaxVars * 64 * sizeof(double));
+    const int bytes = (int)((kMaxVars + 1) * 64 * sizeof(double));
     const void* fns[4] = {reinterpret_cast<const void*>(&gd_step_kernel<2>),
                           reinterpret_cast<const void*>(&gd_step_kernel<3>),
                           reinterpret_cast<const void*>(&gd_step_kernel<4>),
