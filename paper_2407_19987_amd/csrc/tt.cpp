@@ -193,12 +193,16 @@ int tt_upload(TTDev* tt, std::string* err) {
   std::lock_guard<std::mutex> lock(tt->mu);
   if (tt->d_cores) return HOBO_OK;
   double* d = nullptr;
-  if (hipMalloc(reinterpret_cast<void**>(&d), std::max<size_t>(tt->h_cores.size() * 8, 16)) != hipSuccess) {
+  // the cores, then kTTMaxRank zeros: the contraction reads every row whole
+  // (up to its rank limit of columns) and reads rows past a core's rank there
+  std::vector<double> padded(tt->h_cores);
+  padded.resize(padded.size() + kTTMaxRank, 0.0);
+  if (hipMalloc(reinterpret_cast<void**>(&d), padded.size() * 8) != hipSuccess) {
     (void)hipGetLastError();
     *err = "hipMalloc of the TT cores failed";
     return HOBO_ERR_OOM;
   }
-  if (hipMemcpy(d, tt->h_cores.data(), tt->h_cores.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(d, padded.data(), padded.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(d);
     *err = "hipMemcpy of the TT cores failed";
     return HOBO_ERR_HIP;

@@ -4,11 +4,12 @@
 // evaluated left to right as a row vector v <- v M_k(x), O(d n r^2) per
 // replica instead of the dense tensor's O(n^d).  One thread per replica;
 // every lane of a wave walks the same core entries in the same order (the
-// bit only selects a zero or the vector entry).  The work-group copies each
-// core to LDS a slice of variables at a time and its four waves read the
-// rows from there (one address per wave: broadcast reads), instead of each
-// wave fetching them through the scalar cache.  FP64 throughout, one fused
-// multiply-add per (variable, row, column) in that order.
+// bit only selects a zero or the vector entry), so the rows are wave-uniform
+// and come through scalar registers: no per-lane data return.  Each row is
+// read whole (RMAX columns; those past the rank add products that are never
+// used, so no branch per column), a few rows at a time; a row past the rank
+// reads the zeros the upload appends after the cores.  FP64 throughout, one
+// fused multiply-add per (variable, row, column) in that order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -19,24 +20,19 @@
 namespace hobo {
 
 struct TTParams {
-  const double* cores;
+  const double* cores;  // the cores, then kTTMaxRank zeros
   const unsigned long long* bits;
   double* e_out;
   long long B;
   int n, order, W;
   int ranks[kMaxOrder + 1];
   long long off[kMaxOrder];
+  long long zero_off;  // offset of the zeros
 };
-
-constexpr int kTTStage = 4096;  // doubles of a core slice staged in LDS (32 KB)
 
 template <int RMAX>
 __global__ __launch_bounds__(256) void tt_energy_kernel(TTParams p) {
-  // G_k[a][i0 .. i0 + ni)[c], rows (a, i) of r doubles, then RMAX zeros: a
-  // row is read whole (RMAX columns, no branch per column); the columns at or
-  // past r accumulate values that are never used
-  __shared__ double sg[kTTStage + RMAX];
-  for (int e = threadIdx.x; e < RMAX; e += blockDim.x) sg[kTTStage + e] = 0.0;
+  typedef const __attribute__((address_space(4))) double* CD;
   const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = b < p.B;
   unsigned long long xw[4] = {0, 0, 0, 0};
@@ -44,47 +40,37 @@ __global__ __launch_bounds__(256) void tt_energy_kernel(TTParams p) {
   double v[RMAX];
 #pragma unroll
   for (int a = 0; a < RMAX; ++a) v[a] = a == 0 ? 1.0 : 0.0;
+  const CD zero = (CD)p.cores + p.zero_off;
   int rp = 1;
   for (int k = 0; k < p.order; ++k) {
     const int r = p.ranks[k + 1];
-    const double* g = p.cores + p.off[k];
-    const int ni = kTTStage / (rp * r);  // variables per slice (ranks <= 32: at least 4)
+    const CD g = (CD)p.cores + p.off[k];
     double w[RMAX];
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) w[c] = 0.0;
-    for (int i0 = 0; i0 < p.n; i0 += ni) {
-      const int nn = p.n - i0 < ni ? p.n - i0 : ni;
-      __syncthreads();  // the previous slice has been read
-      for (int e = threadIdx.x; e < rp * nn * r; e += blockDim.x) {
-        const int a = e / (nn * r);
-        sg[e] = g[((long long)a * p.n + i0) * r + (e - a * nn * r)];
-      }
-      __syncthreads();
-      for (int ii = 0; ii < nn; ++ii) {
-        const int i = i0 + ii;
-        const int wi = i >> 6;
-        const unsigned long long word = wi == 0 ? xw[0] : wi == 1 ? xw[1] : wi == 2 ? xw[2] : xw[3];
-        const bool on = (word >> (i & 63)) & 1ull;
-        // rows in groups of G, each group's reads in flight together; a row
-        // of the group at or past rp reads the zeros after the slice (v[a] is
-        // +0 there and fma(+0, 0, w) is w, w being never -0)
-        constexpr int G = RMAX >= 32 ? 2 : (RMAX >= 4 ? 4 : RMAX);
+    for (int i = 0; i < p.n; ++i) {
+      const int wi = i >> 6;
+      const unsigned long long word = wi == 0 ? xw[0] : wi == 1 ? xw[1] : wi == 2 ? xw[2] : xw[3];
+      const bool on = (word >> (i & 63)) & 1ull;
+      // rows in groups of G (G x RMAX doubles in scalar registers); a row of
+      // the group past rp reads zeros (v[a] is +0 there and fma(+0, 0, w) is
+      // w, w being never -0)
+      constexpr int G = RMAX >= 32 ? 1 : (RMAX >= 16 ? 2 : 4);
 #pragma unroll
-        for (int a0 = 0; a0 < RMAX; a0 += G) {
-          if (a0 < rp) {
-            double rw[G][RMAX];
+      for (int a0 = 0; a0 < RMAX; a0 += G) {
+        if (a0 < rp) {
+          double rw[G][RMAX];
 #pragma unroll
-            for (int q = 0; q < G; ++q) {
-              const double* row = a0 + q < rp ? sg + ((a0 + q) * nn + ii) * r : sg + kTTStage;
+          for (int q = 0; q < G; ++q) {
+            const CD row = a0 + q < rp ? g + ((long long)(a0 + q) * p.n + i) * r : zero;
 #pragma unroll
-              for (int c = 0; c < RMAX; ++c) rw[q][c] = row[c];
-            }
+            for (int c = 0; c < RMAX; ++c) rw[q][c] = row[c];
+          }
 #pragma unroll
-            for (int q = 0; q < G; ++q) {
-              const double va = on ? v[a0 + q] : 0.0;
+          for (int q = 0; q < G; ++q) {
+            const double va = on ? v[a0 + q] : 0.0;
 #pragma unroll
-              for (int c = 0; c < RMAX; ++c) w[c] = fma(va, rw[q][c], w[c]);
-            }
+            for (int c = 0; c < RMAX; ++c) w[c] = fma(va, rw[q][c], w[c]);
           }
         }
       }
@@ -112,6 +98,7 @@ int launch_tt_energy(const TTDev* tt, const uint64_t* bits, int64_t B, double* e
     rmax = rmax > tt->ranks[(size_t)k] ? rmax : tt->ranks[(size_t)k];
   }
   for (int k = 0; k < tt->order; ++k) p.off[k] = tt->core_off[(size_t)k];
+  p.zero_off = (long long)tt->h_cores.size();
   hipStream_t st = (hipStream_t)stream;
   const dim3 grid((unsigned)((B + 255) / 256)), block(256);
   if (rmax <= 4)
